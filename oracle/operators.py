@@ -1,0 +1,208 @@
+"""Flux-form finite-difference operators of the oracle (Section 3).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.
+
+The paper writes the semi-discrete system in conservation form on equal
+rectangular cells: the tendency of a cell value is minus the x-difference of
+interface fluxes over dx minus the z-difference of interface fluxes over dz
+(Section 3, the flux-difference formula below eq. acousticAd).  Every
+operator here is written that way: an interface flux is computed on the
+x- (or z-) faces, then differenced.  The flux stencils are those of the
+Wicker-Skamarock family the paper cites for orders one to six.
+
+The acoustic-advection system (eq. acousticAd), with constant advection
+velocity U along x and the paper's divergence damping (the modified momentum
+equations of Section 3.2, coefficients of eq. dampingCoeff), reads
+
+    u_t = -U u_x - c_s p_x         + alpha_1 (div u)_x
+    w_t = -U w_x - c_s p_z         + alpha_2 (div u)_z
+    p_t = -U p_x - c_s (u_x + w_z)
+
+Array convention: a field is an (nz, nx) array, x along axis 1.
+``_at(q, m, axis)`` returns the field shifted so that entry i holds q_{i+m}
+(periodic).
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Params:
+    """One KSE-Parareal problem on the periodic unit square.
+
+    nx, nz      cells along x and z (dx = Lx/nx, dz = Lz/nz)
+    c_s, U      sound speed and constant advection velocity along x
+    dt_f, dt_g  fine step (delta t) and coarse step (Delta t)
+    P           number of time slices N_c (one window covering [0, T])
+    T           end time
+    nu_f, nu_c  divergence-damping factors of F and G (eq. dampingCoeff)
+    n_sound     acoustic substeps per coarse step (N_sound, Section 3.2)
+    rank_tol    relative tolerance on |R_jj|/|R_11| for the rank of the
+                pivoted QR in the subspace update (the paper names DGEQP3
+                but no tolerance)
+    """
+
+    nx: int
+    nz: int
+    c_s: float
+    U: float
+    dt_f: float
+    dt_g: float
+    P: int
+    T: float = 1.0
+    nu_f: float = 0.005
+    nu_c: float = 0.1
+    n_sound: int = 4
+    rank_tol: float = 1e-10
+    Lx: float = 1.0
+    Lz: float = 1.0
+
+    @property
+    def dx(self):
+        return self.Lx / self.nx
+
+    @property
+    def dz(self):
+        return self.Lz / self.nz
+
+    @property
+    def d(self):
+        return 3 * self.nx * self.nz
+
+    @property
+    def n_f(self):
+        """Fine steps per slice, N_f = (T/P)/dt_f (Section 2.1)."""
+        return _integer_ratio(self.T / self.P, self.dt_f)
+
+    @property
+    def n_g(self):
+        """Coarse steps per slice, (T/P)/dt_g."""
+        return _integer_ratio(self.T / self.P, self.dt_g)
+
+
+def _integer_ratio(a, b):
+    n = int(round(a / b))
+    if n < 1 or abs(n * b - a) > 1e-9 * abs(a):
+        raise ValueError(f"{a} is not an integer multiple of {b}")
+    return n
+
+
+def _at(q, m, axis):
+    """q_{i+m} along ``axis`` with periodic wrap."""
+    return np.roll(q, -m, axis=axis)
+
+
+# ---------------------------------------------------------------------------
+# Interface fluxes.  Each returns the flux on the face i+1/2 (stored at i).
+# ---------------------------------------------------------------------------
+
+def flux_upwind5(q, vel, axis):
+    """Fifth-order upwind advective flux of the Wicker-Skamarock family:
+    the sixth-order centred flux minus |vel| times a fifth-difference
+    dissipation term.  Valid for either sign of ``vel``."""
+    c6 = (37.0 * (_at(q, 1, axis) + q)
+          - 8.0 * (_at(q, 2, axis) + _at(q, -1, axis))
+          + (_at(q, 3, axis) + _at(q, -2, axis)))
+    dis = ((_at(q, 3, axis) - _at(q, -2, axis))
+           - 5.0 * (_at(q, 2, axis) - _at(q, -1, axis))
+           + 10.0 * (_at(q, 1, axis) - q))
+    return vel / 60.0 * c6 - abs(vel) / 60.0 * dis
+
+
+def flux_upwind1(q, vel, axis):
+    """First-order upwind advective flux: centred average minus |vel|/2
+    times the jump."""
+    return (vel * 0.5 * (q + _at(q, 1, axis))
+            - abs(vel) * 0.5 * (_at(q, 1, axis) - q))
+
+
+def flux_centred4(q, axis):
+    """Fourth-order centred interface value (7(q_i+q_{i+1}) - (q_{i-1}+q_{i+2}))/12."""
+    return (7.0 * (q + _at(q, 1, axis))
+            - (_at(q, -1, axis) + _at(q, 2, axis))) / 12.0
+
+
+def flux_centred2(q, axis):
+    """Second-order centred interface value (q_i + q_{i+1})/2."""
+    return 0.5 * (q + _at(q, 1, axis))
+
+
+def flux_div(flux, h, axis):
+    """(F_{i+1/2} - F_{i-1/2}) / h."""
+    return (flux - _at(flux, -1, axis)) / h
+
+
+# ---------------------------------------------------------------------------
+# Divergence damping: alpha_1 (div u)_x and alpha_2 (div u)_z.
+# div u is evaluated on the faces where it is differenced: on an x-face the
+# normal derivative u_x is the two-point jump and the tangential w_z is the
+# centred z-difference of the face-averaged w; likewise on a z-face.  The
+# face values are then differenced like any flux.
+# ---------------------------------------------------------------------------
+
+def grad_div(u, w, dx, dz):
+    """Return ((div u)_x, (div u)_z) at cell centres."""
+    X, Z = 1, 0
+    w_face = 0.5 * (w + _at(w, 1, X))                     # w on x-faces
+    div_xface = (_at(u, 1, X) - u) / dx + \
+        (_at(w_face, 1, Z) - _at(w_face, -1, Z)) / (2.0 * dz)
+    u_face = 0.5 * (u + _at(u, 1, Z))                     # u on z-faces
+    div_zface = (_at(w, 1, Z) - w) / dz + \
+        (_at(u_face, 1, X) - _at(u_face, -1, X)) / (2.0 * dx)
+    return flux_div(div_xface, dx, X), flux_div(div_zface, dz, Z)
+
+
+# ---------------------------------------------------------------------------
+# Right-hand sides.
+# ---------------------------------------------------------------------------
+
+def rhs_fine(q, prm: Params):
+    """f(q) of the fine propagator F (Section 3.2 and eq. acousticAd):
+    fifth-order upwind advection, fourth-order centred acoustic fluxes and
+    divergence damping with alpha = nu_f * h^2 / dt_f (eq. dampingCoeff,
+    tau = delta t)."""
+    X, Z = 1, 0
+    u, w, p = q
+    dx, dz, c, U = prm.dx, prm.dz, prm.c_s, prm.U
+    ax = prm.nu_f * dx * dx / prm.dt_f
+    az = prm.nu_f * dz * dz / prm.dt_f
+    gdx, gdz = grad_div(u, w, dx, dz)
+    fu = (-flux_div(flux_upwind5(u, U, X), dx, X)
+          - c * flux_div(flux_centred4(p, X), dx, X) + ax * gdx)
+    fw = (-flux_div(flux_upwind5(w, U, X), dx, X)
+          - c * flux_div(flux_centred4(p, Z), dz, Z) + az * gdz)
+    fp = (-flux_div(flux_upwind5(p, U, X), dx, X)
+          - c * (flux_div(flux_centred4(u, X), dx, X)
+                 + flux_div(flux_centred4(w, Z), dz, Z)))
+    return np.stack([fu, fw, fp])
+
+
+def coarse_slow_tendency(q, prm: Params):
+    """Slow (advective) tendency of the partially split coarse scheme:
+    first-order upwind advection, evaluated once per coarse step and held
+    fixed over its acoustic substeps (Section 3.2)."""
+    X = 1
+    return np.stack([-flux_div(flux_upwind1(f, prm.U, X), prm.dx, X)
+                     for f in q])
+
+
+def acoustic_substep(q, R, dtau, prm: Params):
+    """One forward-backward acoustic substep of length dtau = Delta t/N_sound
+    (Section 3.2): momentum forward with the old pressure and divergence
+    damping (alpha = nu_c h^2 / dtau), then pressure backward with the new
+    velocities.  ``R`` is the frozen slow tendency."""
+    X, Z = 1, 0
+    u, w, p = q
+    dx, dz, c = prm.dx, prm.dz, prm.c_s
+    ax = prm.nu_c * dx * dx / dtau
+    az = prm.nu_c * dz * dz / dtau
+    gdx, gdz = grad_div(u, w, dx, dz)
+    un = u + dtau * (R[0] - c * flux_div(flux_centred2(p, X), dx, X)
+                     + ax * gdx)
+    wn = w + dtau * (R[1] - c * flux_div(flux_centred2(p, Z), dz, Z)
+                     + az * gdz)
+    pn = p + dtau * (R[2] - c * (flux_div(flux_centred2(un, X), dx, X)
+                                 + flux_div(flux_centred2(wn, Z), dz, Z)))
+    return np.stack([un, wn, pn])

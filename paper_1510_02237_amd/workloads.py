@@ -1,0 +1,157 @@
+"""Seeded synthetic workloads: problem parameters and initial conditions.
+
+This module holds no arithmetic of the method.  It only draws inputs (grid,
+physical and time-step parameters, initial states, request streams) so that
+the HIP library and the test oracle receive the same arrays.  It imports
+nothing but numpy.
+
+State layout: float64 array (3, nz, nx), fields (u, w, p), x fastest.
+
+Parameter readings (the paper's own test case uses a rotating flow; these
+workloads use constant U along x):
+  * fine step  dt_f = 0.2 * min(dx, dz) / c_s   (fine CFL 0.2, Section 3.2)
+  * coarse step dt_g = 10 * dt_f                 (coarse CFL 2.0, Table 1)
+  * nu_f = 0.005, nu_c = 0.1 (Section 3.2)
+  * N_sound: the smallest of 4, 6, 8, 10 for which the split-explicit coarse
+    propagator is stable at the given U (4 up to U = 0.15, 6 up to 0.2,
+    8 up to 0.25, 10 up to 0.3); the paper raises N_sound the same way to
+    keep G stable (Section 3.2.3)
+  * one window: P slices of length T/P, T = 1
+"""
+
+import math
+
+import numpy as np
+
+NU_F = 0.005
+NU_C = 0.1
+RANK_TOL = 1e-10
+
+
+def n_sound_for(U):
+    """Minimum stable number of acoustic substeps for |U| <= 0.3."""
+    a = abs(U)
+    for limit, ns in ((0.15, 4), (0.2, 6), (0.25, 8), (0.3, 10)):
+        if a <= limit + 1e-12:
+            return ns
+    raise ValueError(f"no stable N_sound tabulated for U={U}")
+
+
+def problem(nx, nz, P, U=0.1, c_s=1.0, T=1.0, cfl_f=0.2, coarse_ratio=10,
+            n_sound=None):
+    """Plain dict of problem parameters shared by the library and the oracle."""
+    dt_f = cfl_f * min(1.0 / nx, 1.0 / nz) / c_s
+    return dict(nx=int(nx), nz=int(nz), c_s=float(c_s), U=float(U),
+                dt_f=dt_f, dt_g=coarse_ratio * dt_f, P=int(P), T=float(T),
+                nu_f=NU_F, nu_c=NU_C,
+                n_sound=int(n_sound if n_sound is not None else n_sound_for(U)),
+                rank_tol=RANK_TOL)
+
+
+def _cell_centres(nx, nz):
+    x = (np.arange(nx) + 0.5) / nx
+    z = (np.arange(nz) + 0.5) / nz
+    return np.meshgrid(x, z)  # (nz, nx) each
+
+
+def gaussian_bump(nx, nz, centre, width=0.05, amp=1.0):
+    """amp * exp(-(dx^2 + dz^2) / (2 width^2)) with periodic minimum-image
+    distances to ``centre`` on the unit square."""
+    X, Z = _cell_centres(nx, nz)
+    ddx = X - centre[0]
+    ddz = Z - centre[1]
+    ddx -= np.round(ddx)
+    ddz -= np.round(ddz)
+    return amp * np.exp(-(ddx * ddx + ddz * ddz) / (2.0 * width * width))
+
+
+def ic_bumps(nx, nz, seed, nbumps=1, noise=0.0, width=0.05, amp=1.0):
+    """Pressure = sum of ``nbumps`` Gaussian bumps at uniformly drawn centres;
+    u, w = N(0, noise^2) i.i.d. per point (zero when noise == 0)."""
+    rng = np.random.default_rng(seed)
+    q = np.zeros((3, nz, nx))
+    for _ in range(nbumps):
+        c = rng.random(2)
+        q[2] += gaussian_bump(nx, nz, c, width, amp)
+    if noise > 0.0:
+        q[0] += rng.normal(0.0, noise, (nz, nx))
+        q[1] += rng.normal(0.0, noise, (nz, nx))
+    return q
+
+
+def ic_fourier(nx, nz, seed, nmodes=32, kmax=64):
+    """Pressure = sum of ``nmodes`` random-phase Fourier modes
+    cos(2 pi (kx x + kz z) + phi) / sqrt(nmodes) with integer
+    1 <= max(|kx|, |kz|) <= kmax; u = w = 0."""
+    rng = np.random.default_rng(seed)
+    X, Z = _cell_centres(nx, nz)
+    q = np.zeros((3, nz, nx))
+    m = 0
+    while m < nmodes:
+        kx, kz = rng.integers(-kmax, kmax + 1, size=2)
+        if max(abs(kx), abs(kz)) == 0:
+            continue
+        phi = rng.random() * 2.0 * math.pi
+        q[2] += np.cos(2.0 * math.pi * (kx * X + kz * Z) + phi)
+        m += 1
+    q[2] /= math.sqrt(nmodes)
+    return q
+
+
+# The five workloads: small oracle-scale run, single plain solve, batched
+# fused solve, serving stream, large single instance.
+CONFIGS = {
+    "c1_64x32": dict(nx=64, nz=32, P=8, K=3, U=0.1, seed=1,
+                     ic=dict(kind="bumps", nbumps=1)),
+    "c2_512x256": dict(nx=512, nz=256, P=32, K=4, U=0.1, seed=2,
+                       ic=dict(kind="bumps", nbumps=4, noise=1e-3)),
+    "c3_1024x512": dict(nx=1024, nz=512, P=64, K=5, U=0.1, seed=3,
+                        ic=dict(kind="bumps", nbumps=4, noise=1e-3)),
+    "c5_4096x1024": dict(nx=4096, nz=1024, P=128, K=4, U=0.2, seed=5,
+                         ic=dict(kind="fourier", nmodes=32, kmax=64)),
+}
+
+
+def config(name):
+    """(problem dict, K, initial state) of a named workload."""
+    c = CONFIGS[name]
+    prob = problem(c["nx"], c["nz"], c["P"], U=c["U"])
+    ic = dict(c["ic"])
+    kind = ic.pop("kind")
+    if kind == "bumps":
+        u0 = ic_bumps(c["nx"], c["nz"], c["seed"], **ic)
+    else:
+        u0 = ic_fourier(c["nx"], c["nz"], c["seed"], **ic)
+    return prob, c["K"], u0
+
+
+SERVE_GRIDS = ((128, 64), (256, 128), (512, 256), (1024, 512))
+SERVE_SLICES = (8, 16, 32, 64)
+
+
+def serving_stream(n_requests, rate_per_s, seed=4, grids=SERVE_GRIDS,
+                   slices=SERVE_SLICES, K=4):
+    """Seeded Poisson stream of KSE-Parareal requests.
+
+    Each request: grid uniform over ``grids``, U ~ U[0, 0.3], P uniform over
+    ``slices``, K fixed, 1-4 Gaussian pressure bumps.  Arrival times are the
+    cumulative sums of Exp(rate) gaps.  Returns a list of dicts with keys
+    t_arrival, prob, K, u0 (u0 is generated lazily by ``request_state``).
+    """
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for r in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        nx, nz = grids[rng.integers(len(grids))]
+        P = int(slices[rng.integers(len(slices))])
+        U = float(rng.uniform(0.0, 0.3))
+        nb = int(rng.integers(1, 5))
+        reqs.append(dict(id=r, t_arrival=t, prob=problem(nx, nz, P, U=U), K=K,
+                         ic_seed=int(rng.integers(1 << 31)), nbumps=nb))
+    return reqs
+
+
+def request_state(req):
+    p = req["prob"]
+    return ic_bumps(p["nx"], p["nz"], req["ic_seed"], nbumps=req["nbumps"])
