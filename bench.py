@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Benchmark of the KSE-Parareal hot path on one MI355X.
+
+A step is one whole KSE-Parareal solve (coarse initialisation, then K times
+fine sweep over all slices, subspace update and serial correction) of the
+single-solve workload: 512 x 256 grid, c_s = 1, U = 0.1, P = 32 slices over
+T = 1, K = 4 iterations, 4 seeded Gaussian pressure bumps plus N(0, 1e-3)
+noise on u, w, FP64.  The initial state is resident in HBM before the timed
+region.  `value` is solves per second through the batched form (one fused
+fine-step launch over all slices per RK-3 step, replayed from a HIP graph).
+
+Also reported on the same workload: the plain form (one launch per slice),
+the serial GPU fine run F^P(u0) with the epsilon of eq. errorDef beside
+each time, the fused fine-step kernel against the HBM roofline (48 bytes
+per grid-point step, timed with HIP events on the library stream), a short
+served stream (p50/p99 latency, solves/s), and the CPU oracle on a bounded
+sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+BYTES_PER_POINT_STEP = 48.0   # read and write u, w, p once per RK-3 step
+
+
+def _rel_l2(a, b):
+    import numpy as np
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def timed_solves(ctx, u0, K, out, n):
+    import torch
+    torch.cuda.synchronize()
+    ms_fine = 0.0
+    pts = 0
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ctx.solve(u0, K, out=out)
+        st = ctx.stats()
+        ms_fine += st["ms_fine"]
+        pts += st["fine_point_steps"]
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / n, ms_fine, pts, st
+
+
+def serve_leg(n_req, rate, seed=4, timeout=300.0):
+    """Poisson stream of KSE-Parareal requests (grids 128x64..1024x512,
+    U in [0, 0.3], P in {8,...,64}, K = 4) through the server."""
+    import ctypes
+    import numpy as np
+    from paper_1510_02237_amd import binding, workloads as W
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    rc = lib.pr_server_create(0, 0, 8, ctypes.byref(h))
+    if rc:
+        raise RuntimeError(f"pr_server_create: {rc}")
+    reqs = W.serving_stream(n_req, rate, seed=seed)
+    states = [W.request_state(r) for r in reqs]
+    tickets = []
+    lat = []
+    t_start = time.perf_counter()
+    try:
+        for r, u0 in zip(reqs, states):
+            while time.perf_counter() - t_start < r["t_arrival"]:
+                time.sleep(0.0005)
+            p = r["prob"]
+            o = binding.default_opts(nu_f=p["nu_f"], nu_c=p["nu_c"],
+                                     n_sound=p["n_sound"],
+                                     rank_tol=p["rank_tol"])
+            t = ctypes.c_uint64()
+            rc = lib.pr_submit_ex(h, ctypes.byref(binding.grid(p["nx"], p["nz"], p["T"])),
+                                  p["c_s"], p["U"], p["dt_f"], p["dt_g"], p["P"],
+                                  r["K"], ctypes.byref(o), u0.ctypes.data,
+                                  ctypes.byref(t))
+            if rc:
+                raise RuntimeError(f"pr_submit: {rc}")
+            tickets.append((t.value, u0.shape))
+        for t, shape in tickets:
+            out = np.empty(shape)
+            l = ctypes.c_double()
+            while True:
+                rc = lib.pr_poll(h, t, out.ctypes.data, ctypes.byref(l))
+                if rc != binding.PR_EAGAIN:
+                    break
+                if time.perf_counter() - t_start > timeout:
+                    raise RuntimeError("served stream timed out")
+                time.sleep(0.001)
+            if rc:
+                raise RuntimeError(f"request failed: {rc}")
+            lat.append(l.value)
+        wall = time.perf_counter() - t_start
+    finally:
+        lib.pr_server_destroy(h)
+    lat = np.array(lat) * 1e3
+    return dict(requests=n_req, arrival_rate_per_s=rate,
+                p50_ms=float(np.percentile(lat, 50)),
+                p99_ms=float(np.percentile(lat, 99)),
+                solves_per_s=n_req / wall, wall_s=wall)
+
+
+def cpu_baseline(prob, u0, K):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    one full-slice fine propagation F (n_f RK-3 steps) and three coarse
+    propagations G.  Solves/s = 1 / (P K t_F + (P + 2 P K) t_G): the oracle's
+    own counts of F and G calls per solve (it applies K twice per slice);
+    its projections and pivoted QRs are not counted, which favours it."""
+    import oracle
+    from oracle.operators import Params
+    prm = Params(**prob)
+    t0 = time.perf_counter()
+    oracle.fine_F(u0, prm)
+    tF = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(3):
+        oracle.coarse_G(u0, prm)
+    tG = (time.perf_counter() - t0) / 3
+    P = prob["P"]
+    t_solve = P * K * tF + (P + 2 * P * K) * tG
+    return dict(value=1.0 / t_solve, unit="solves/s", cores=1, kind="oracle",
+                sample=(f"oracle.fine_F on one {prob['nx']}x{prob['nz']} slice "
+                        f"({prm.n_f} RK-3 steps, {tF:.2f} s) and oracle.coarse_G "
+                        f"({prm.n_g} steps, {tG:.3f} s); solve time extrapolated "
+                        f"as {P}*{K} F + {P + 2 * P * K} G = {t_solve:.0f} s "
+                        "(projections and QR not counted)"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2_512x256")
+    ap.add_argument("--serve", type=int, default=24,
+                    help="requests in the served-latency leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=6.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed batched solves (for profiling)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the method is parallel in time within one device here",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1510_02237_amd import binding, workloads as W
+
+    prob, K, u0 = W.config(args.workload)
+    dev = torch.device("cuda:0")
+    u0_d = torch.from_numpy(u0).to(dev)
+    out = torch.empty_like(u0_d)
+    ctx = binding.Context.from_problem(prob, form="batched")
+    for _ in range(args.warmup):
+        ctx.solve(u0_d, K, out=out)
+    ms, ms_fine, pts, st = timed_solves(ctx, u0_d, K, out, args.steps)
+    n_fine_launches = args.steps * K * ctx_nf(prob)
+    kernel_ms = ms_fine / n_fine_launches
+    achieved = BYTES_PER_POINT_STEP * pts / (ms_fine * 1e-3) / 1e9
+    res = dict(
+        metric="Parareal wall-time vs serial fine on GPU; stencil GB/s; "
+               "p50/p99 served latency",
+        value=1000.0 / ms, unit="solves/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+        scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload=args.workload, grid=[prob["nx"], prob["nz"]],
+                    P=prob["P"], K=K, U=prob["U"], c_s=prob["c_s"],
+                    T=prob["T"], n_f=ctx_nf(prob), n_g=ctx_ng(prob),
+                    form="batched", parallelism="time slices x tiles, 1 GPU"),
+        phases_ms=dict(coarse_init=st["ms_coarse_init"], fine=st["ms_fine"],
+                       update=st["ms_update"], chain=st["ms_chain"],
+                       total=st["ms_total"]),
+        ranks=st["rank"],
+        roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS,
+                      unit="GB/s", frac=achieved / HBM_PEAK_GBPS, traffic=None,
+                      kernel="k_fine_step", kernel_avg_ms=kernel_ms,
+                      bytes_per_point_step=BYTES_PER_POINT_STEP),
+        fine_point_updates_per_s=pts / (ms_fine * 1e-3),
+    )
+    if not args.no_extras:
+        ref = ctx.serial_fine(u0_d).cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ser = ctx.serial_fine(u0_d)
+        torch.cuda.synchronize()
+        ser_ms = (time.perf_counter() - t0) * 1e3
+        eps_b = _rel_l2(out.cpu().numpy(), ref)
+        plain = binding.Context.from_problem(prob, form="plain")
+        plain.solve(u0_d, K, out=out)
+        pms, _, _, _ = timed_solves(plain, u0_d, K, out, max(1, args.steps // 2))
+        eps_p = _rel_l2(out.cpu().numpy(), ref)
+        coarse_only = ctx.solve(u0_d, 0).cpu().numpy()
+        res["time_to_solution_ms"] = dict(
+            batched=ms, plain=pms, serial_fine=ser_ms,
+            eps_batched=eps_b, eps_plain=eps_p,
+            eps_coarse_only=_rel_l2(coarse_only, ref),
+            speedup_batched_vs_plain=pms / ms,
+            speedup_batched_vs_serial_fine=ser_ms / ms)
+        del ser
+        if args.serve > 0:
+            res["served"] = serve_leg(args.serve, args.serve_rate)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(prob, u0, K)
+        res["cpu_baseline"]["cpu_model"] = cpu_model()
+        res["cpu_baseline"]["nproc"] = os.cpu_count()
+    print(json.dumps(res))
+
+
+def ctx_nf(prob):
+    return int(round(prob["T"] / prob["P"] / prob["dt_f"]))
+
+
+def ctx_ng(prob):
+    return int(round(prob["T"] / prob["P"] / prob["dt_g"]))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

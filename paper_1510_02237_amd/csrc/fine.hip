@@ -1,0 +1,345 @@
+// Fine propagator kernels: one step of the three-stage Runge-Kutta scheme
+// (stages at 1/3, 1/2 and 1 of the step, each restarting from q^n) applied
+// to the semi-discrete acoustic-advection system with 5th-order upwind
+// advection, 4th-order centred acoustic terms and divergence damping
+// (Section 3, Section 3.2, eq. acousticAd, eq. dampingCoeff).
+//
+// k_fine_step: all three stages of one step fused in a single pass.  A
+// workgroup owns an x-range of NT input columns (one per thread, x fastest
+// in memory so every row load is coalesced) and marches down a chunk of
+// rows in z.  Each input row goes once into an LDS ring; stage 1 runs two
+// rows behind the loads, stage 2 two rows behind stage 1 and stage 3 two
+// rows behind stage 2, so that every row a stage needs has been produced in
+// an earlier iteration and one barrier per row suffices.  Neighbours along
+// x come from the LDS rings, neighbours along z from per-thread register
+// windows.  The halo is 3 columns on the upwind side and 2 on the other per
+// stage (15 per step) and 6 rows above and below the chunk.
+#include "pr_internal.h"
+
+namespace prh {
+namespace {
+
+__device__ __forceinline__ void lds_barrier() {
+  // Wait for this wave's LDS traffic only, then join the workgroup; global
+  // loads of prefetched rows stay in flight across the barrier.
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Workgroups are handed to the 8 XCDs round-robin; give each XCD a
+// contiguous range of logical tiles so neighbouring tiles, which read the
+// same halo rows, share an L2.
+__device__ __forceinline__ int xcd_logical_block(int nlogical) {
+  const int b = blockIdx.x;
+  const int per = (nlogical + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+struct Coef {
+  double a0, a1, a2, a3, a4, a5, cx4, cz4, kxx, kxzu, kzz, kxzw;
+};
+
+__device__ __forceinline__ Coef load_coef(const FineCoef& c) {
+  return Coef{c.adv[0], c.adv[1], c.adv[2], c.adv[3], c.adv[4], c.adv[5],
+              c.cx4,    c.cz4,    c.kxx,    c.kxzu,   c.kzz,    c.kxzw};
+}
+
+// Right-hand side at one point.  rc, rm, rp: LDS rows r, r-1, r+1 of the
+// level (each [3][W], field order u, w, p); c: this thread's column in the
+// padded row.  The own-column values along z come from registers.
+template <int SGN, int W>
+__device__ __forceinline__ void rhs_point(
+    const double (*rc)[W], const double (*rm)[W], const double (*rp)[W],
+    int c, double u0, double wm2, double wm1, double w0, double wp1,
+    double wp2, double pm2, double pm1, double p0, double pp1, double pp2,
+    const Coef& k, double& fu, double& fw, double& fp) {
+  const double* U = rc[0];
+  const double* Wr = rc[1];
+  const double* Pr = rc[2];
+  const double um2 = U[c - 2], um1 = U[c - 1], up1 = U[c + 1], up2 = U[c + 2];
+  const double wxm2 = Wr[c - 2], wxm1 = Wr[c - 1], wxp1 = Wr[c + 1],
+               wxp2 = Wr[c + 2];
+  const double pxm2 = Pr[c - 2], pxm1 = Pr[c - 1], pxp1 = Pr[c + 1],
+               pxp2 = Pr[c + 2];
+  double au, aw, ap;
+  if (SGN > 0) {  // offsets -3 .. +2
+    au = k.a0 * U[c - 3] + k.a1 * um2 + k.a2 * um1 + k.a3 * u0 + k.a4 * up1 +
+         k.a5 * up2;
+    aw = k.a0 * Wr[c - 3] + k.a1 * wxm2 + k.a2 * wxm1 + k.a3 * w0 +
+         k.a4 * wxp1 + k.a5 * wxp2;
+    ap = k.a0 * Pr[c - 3] + k.a1 * pxm2 + k.a2 * pxm1 + k.a3 * p0 +
+         k.a4 * pxp1 + k.a5 * pxp2;
+  } else {  // offsets -2 .. +3
+    au = k.a0 * um2 + k.a1 * um1 + k.a2 * u0 + k.a3 * up1 + k.a4 * up2 +
+         k.a5 * U[c + 3];
+    aw = k.a0 * wxm2 + k.a1 * wxm1 + k.a2 * w0 + k.a3 * wxp1 + k.a4 * wxp2 +
+         k.a5 * Wr[c + 3];
+    ap = k.a0 * pxm2 + k.a1 * pxm1 + k.a2 * p0 + k.a3 * pxp1 + k.a4 * pxp2 +
+         k.a5 * Pr[c + 3];
+  }
+  // Cross terms of the grad-div damping: w and u at (i+-1, j+-1).
+  const double wpp = rp[1][c + 1], wpm = rm[1][c + 1];
+  const double wmp = rp[1][c - 1], wmm = rm[1][c - 1];
+  const double upp = rp[0][c + 1], upm = rm[0][c + 1];
+  const double ump = rp[0][c - 1], umm = rm[0][c - 1];
+  const double dx4p = (pxm2 - pxp2) + 8.0 * (pxp1 - pxm1);
+  const double dz4p = (pm2 - pp2) + 8.0 * (pp1 - pm1);
+  const double dx4u = (um2 - up2) + 8.0 * (up1 - um1);
+  const double dz4w = (wm2 - wp2) + 8.0 * (wp1 - wm1);
+  fu = au - k.cx4 * dx4p + k.kxx * ((up1 + um1) - 2.0 * u0) +
+       k.kxzu * ((wpp - wpm) - (wmp - wmm));
+  fw = aw - k.cz4 * dz4p + k.kzz * ((wp1 + wm1) - 2.0 * w0) +
+       k.kxzw * ((upp - ump) - (upm - umm));
+  fp = ap - k.cx4 * dx4u - k.cz4 * dz4w;
+}
+
+template <int SGN, int NT, int PF>
+__global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
+  constexpr int HL = SGN > 0 ? 3 : 2;  // reach on the upwind side
+  constexpr int HR = 5 - HL;
+  constexpr int TX = NT - 15;
+  constexpr int PAD = 3;
+  constexpr int W = NT + 2 * PAD;
+  static_assert(8 % PF == 0, "prefetch depth must divide the unroll");
+  __shared__ double ring[3][4][3][W];  // level, row slot, field, column
+
+  const int lb = xcd_logical_block(L.nblocks);
+  if (lb >= L.nblocks) return;
+  int j = 0;
+#pragma unroll 1
+  while (j + 1 < L.njobs && lb >= L.job[j + 1].block_begin) ++j;
+  const FineJob& J = L.job[j];
+
+  const int local = lb - J.block_begin;
+  const int xt = local % J.xtiles;
+  const int rest = local / J.xtiles;
+  const int zt = rest % J.ztiles;
+  const int sl = rest / J.ztiles;
+  const int nx = J.nx, nz = J.nz;
+  const int64_t n = (int64_t)nx * nz;
+  const double* __restrict__ in = J.in + sl * J.in_stride;
+  double* __restrict__ out = J.out + sl * J.out_stride;
+  const Coef k = load_coef(J.c);
+  const double dt = J.c.dt;
+  const double b1 = dt / 3.0, b2 = 0.5 * dt;
+
+  const int t = threadIdx.x;
+  const int c = PAD + t;
+  const int zc = L.zc;
+  const int x0 = xt * TX;
+  const int z0 = zt * zc;
+  const int gx = wrap(x0 - 3 * HL + t, nx);
+  const int xo = x0 + t - 3 * HL;
+  const bool store_col = (t >= 3 * HL) && (t < NT - 3 * HR) && (xo < nx);
+  const int nrows = zc + 12;
+
+  // Pads of every ring row are read by the edge columns (whose results are
+  // discarded); keep them finite.
+  for (int q = t; q < 3 * 4 * 3 * 2 * PAD; q += NT) {
+    const int row = q / (2 * PAD), e = q % (2 * PAD);
+    double* r = &ring[0][0][0][0] + row * W;
+    r[e < PAD ? e : NT + e] = 0.0;
+  }
+
+  double fu_[PF], fw_[PF], fp_[PF];  // prefetched input rows
+#pragma unroll
+  for (int q = 0; q < PF; ++q) {
+    if (q < nrows) {
+      const double* src = in + (int64_t)wrap(z0 - 6 + q, nz) * nx + gx;
+      fu_[q] = src[0];
+      fw_[q] = src[n];
+      fp_[q] = src[2 * n];
+    }
+  }
+
+  double iu[8], iw[8], ip[8];  // input rows, indexed by iteration & 7
+  double au[8], aw[8], ap[8];  // stage-1 rows
+  double bu[8], bw[8], bp[8];  // stage-2 rows
+
+  for (int base = 0; base < nrows; base += 8) {
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu) {
+      const int it = base + uu;
+      if (it >= nrows) break;
+      lds_barrier();
+      // Input row z0 - 6 + it.
+      {
+        const int q = uu % PF;
+        iu[uu] = fu_[q];
+        iw[uu] = fw_[q];
+        ip[uu] = fp_[q];
+        ring[0][uu & 3][0][c] = iu[uu];
+        ring[0][uu & 3][1][c] = iw[uu];
+        ring[0][uu & 3][2][c] = ip[uu];
+        if (it + PF < nrows) {
+          const double* src =
+              in + (int64_t)wrap(z0 - 6 + it + PF, nz) * nx + gx;
+          fu_[q] = src[0];
+          fw_[q] = src[n];
+          fp_[q] = src[2 * n];
+        }
+      }
+      // Stage 1 on the input row of iteration it-2:
+      // q* = q^n + dt/3 f(q^n).
+      if (it >= 4) {
+        double fu, fw, fp;
+        rhs_point<SGN, W>(ring[0][(uu - 2) & 3], ring[0][(uu - 3) & 3],
+                          ring[0][(uu - 1) & 3], c, iu[(uu - 2) & 7],
+                          iw[(uu - 4) & 7], iw[(uu - 3) & 7],
+                          iw[(uu - 2) & 7], iw[(uu - 1) & 7], iw[uu & 7],
+                          ip[(uu - 4) & 7], ip[(uu - 3) & 7],
+                          ip[(uu - 2) & 7], ip[(uu - 1) & 7], ip[uu & 7], k,
+                          fu, fw, fp);
+        au[uu] = iu[(uu - 2) & 7] + b1 * fu;
+        aw[uu] = iw[(uu - 2) & 7] + b1 * fw;
+        ap[uu] = ip[(uu - 2) & 7] + b1 * fp;
+        ring[1][uu & 3][0][c] = au[uu];
+        ring[1][uu & 3][1][c] = aw[uu];
+        ring[1][uu & 3][2][c] = ap[uu];
+      }
+      // Stage 2 on the stage-1 row of iteration it-2 (input row of it-4):
+      // q** = q^n + dt/2 f(q*).
+      if (it >= 8) {
+        double fu, fw, fp;
+        rhs_point<SGN, W>(ring[1][(uu - 2) & 3], ring[1][(uu - 3) & 3],
+                          ring[1][(uu - 1) & 3], c, au[(uu - 2) & 7],
+                          aw[(uu - 4) & 7], aw[(uu - 3) & 7],
+                          aw[(uu - 2) & 7], aw[(uu - 1) & 7], aw[uu & 7],
+                          ap[(uu - 4) & 7], ap[(uu - 3) & 7],
+                          ap[(uu - 2) & 7], ap[(uu - 1) & 7], ap[uu & 7], k,
+                          fu, fw, fp);
+        bu[uu] = iu[(uu - 4) & 7] + b2 * fu;
+        bw[uu] = iw[(uu - 4) & 7] + b2 * fw;
+        bp[uu] = ip[(uu - 4) & 7] + b2 * fp;
+        ring[2][uu & 3][0][c] = bu[uu];
+        ring[2][uu & 3][1][c] = bw[uu];
+        ring[2][uu & 3][2][c] = bp[uu];
+      }
+      // Stage 3 on the stage-2 row of iteration it-2 (input row of it-6):
+      // q^{n+1} = q^n + dt f(q**), written out.
+      if (it >= 12) {
+        double fu, fw, fp;
+        rhs_point<SGN, W>(ring[2][(uu - 2) & 3], ring[2][(uu - 3) & 3],
+                          ring[2][(uu - 1) & 3], c, bu[(uu - 2) & 7],
+                          bw[(uu - 4) & 7], bw[(uu - 3) & 7],
+                          bw[(uu - 2) & 7], bw[(uu - 1) & 7], bw[uu & 7],
+                          bp[(uu - 4) & 7], bp[(uu - 3) & 7],
+                          bp[(uu - 2) & 7], bp[(uu - 1) & 7], bp[uu & 7], k,
+                          fu, fw, fp);
+        const int z3 = z0 + it - 12;
+        if (store_col && z3 < nz) {
+          double* dst = out + (int64_t)z3 * nx + xo;
+          dst[0] = iu[(uu - 6) & 7] + dt * fu;
+          dst[n] = iw[(uu - 6) & 7] + dt * fw;
+          dst[2 * n] = ip[(uu - 6) & 7] + dt * fp;
+        }
+      }
+    }
+  }
+}
+
+// Unfused stage: out = base + beta f(in), one point per thread, neighbours
+// straight from global memory.
+template <int SGN>
+__global__ __launch_bounds__(256) void k_fine_stage(
+    const double* __restrict__ in, int64_t is, const double* __restrict__ base,
+    int64_t bs, double* __restrict__ out, int64_t os, int nx, int nz,
+    const FineCoef cc, double beta) {
+  const int64_t n = (int64_t)nx * nz;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const int64_t sl = blockIdx.y;
+  const double* U = in + sl * is;
+  const double* Wf = U + n;
+  const double* Pf = U + 2 * n;
+  const int i = (int)(idx % nx), jz = (int)(idx / nx);
+  auto X = [&](int di) { return wrap(i + di, nx); };
+  auto Z = [&](int dj) { return (int64_t)wrap(jz + dj, nz) * nx; };
+  const int64_t zr = (int64_t)jz * nx;
+  const Coef k = load_coef(cc);
+  const int m0 = SGN > 0 ? -3 : -2;
+  const double a[6] = {k.a0, k.a1, k.a2, k.a3, k.a4, k.a5};
+  double au = 0.0, aw = 0.0, ap = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int64_t o = zr + X(m0 + q);
+    au += a[q] * U[o];
+    aw += a[q] * Wf[o];
+    ap += a[q] * Pf[o];
+  }
+  const double u0 = U[idx], w0 = Wf[idx];
+  const double dx4p = (Pf[zr + X(-2)] - Pf[zr + X(2)]) +
+                      8.0 * (Pf[zr + X(1)] - Pf[zr + X(-1)]);
+  const double dz4p = (Pf[Z(-2) + i] - Pf[Z(2) + i]) +
+                      8.0 * (Pf[Z(1) + i] - Pf[Z(-1) + i]);
+  const double dx4u = (U[zr + X(-2)] - U[zr + X(2)]) +
+                      8.0 * (U[zr + X(1)] - U[zr + X(-1)]);
+  const double dz4w = (Wf[Z(-2) + i] - Wf[Z(2) + i]) +
+                      8.0 * (Wf[Z(1) + i] - Wf[Z(-1) + i]);
+  const double gxx = (U[zr + X(1)] + U[zr + X(-1)]) - 2.0 * u0;
+  const double gzz = (Wf[Z(1) + i] + Wf[Z(-1) + i]) - 2.0 * w0;
+  const double wx = (Wf[Z(1) + X(1)] - Wf[Z(-1) + X(1)]) -
+                    (Wf[Z(1) + X(-1)] - Wf[Z(-1) + X(-1)]);
+  const double uz = (U[Z(1) + X(1)] - U[Z(1) + X(-1)]) -
+                    (U[Z(-1) + X(1)] - U[Z(-1) + X(-1)]);
+  const double fu = au - k.cx4 * dx4p + k.kxx * gxx + k.kxzu * wx;
+  const double fw = aw - k.cz4 * dz4p + k.kzz * gzz + k.kxzw * uz;
+  const double fp = ap - k.cx4 * dx4u - k.cz4 * dz4w;
+  const double* B = base + sl * bs;
+  double* O = out + sl * os;
+  O[idx] = B[idx] + beta * fu;
+  O[n + idx] = B[n + idx] + beta * fw;
+  O[2 * n + idx] = B[2 * n + idx] + beta * fp;
+}
+
+template <int SGN, int NT>
+hipError_t launch_nt(const FineLaunch& L, hipStream_t s) {
+  const int grid = 8 * ((L.nblocks + 7) / 8);
+  hipLaunchKernelGGL((k_fine_step<SGN, NT, 4>), dim3(grid), dim3(NT), 0, s,
+                     L);
+  return hipGetLastError();
+}
+
+template <int SGN>
+hipError_t launch_sgn(const FineLaunch& L, int nt, hipStream_t s) {
+  switch (nt) {
+    case 128: return launch_nt<SGN, 128>(L, s);
+    case 192: return launch_nt<SGN, 192>(L, s);
+    case 256: return launch_nt<SGN, 256>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool fine_nt_supported(int nt) {
+  return nt == 128 || nt == 192 || nt == 256;
+}
+
+hipError_t launch_fine_step(const FineLaunch& L, int nt, int sgn,
+                            hipStream_t s) {
+  if (L.nblocks <= 0) return hipSuccess;
+  return sgn >= 0 ? launch_sgn<1>(L, nt, s) : launch_sgn<-1>(L, nt, s);
+}
+
+hipError_t launch_fine_stage(const double* in, int64_t in_stride,
+                             const double* base, int64_t base_stride,
+                             double* out, int64_t out_stride, int nx, int nz,
+                             int nslices, const FineCoef& c, double beta,
+                             int sgn, hipStream_t s) {
+  const int64_t n = (int64_t)nx * nz;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)nslices);
+  if (sgn >= 0)
+    hipLaunchKernelGGL(k_fine_stage<1>, grid, dim3(256), 0, s, in, in_stride,
+                       base, base_stride, out, out_stride, nx, nz, c, beta);
+  else
+    hipLaunchKernelGGL(k_fine_stage<-1>, grid, dim3(256), 0, s, in, in_stride,
+                       base, base_stride, out, out_stride, nx, nz, c, beta);
+  return hipGetLastError();
+}
+
+}  // namespace prh

@@ -1,0 +1,139 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every entry point its header declares, and its host logic (argument
+validation, the von Neumann stability scan, footprints) is right.
+
+The stability scan is pinned against the amplification matrices the oracle
+tests build from the stencil weights (test_oracle_propagators), with numpy's
+eigenvalue routine: an independent formulation of the same symbols.
+"""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1510_02237_amd import binding, workloads as W
+from oracle.operators import Params
+from test_oracle_operators import fine_symbol
+from test_oracle_propagators import coarse_step_symbol, rk3_poly
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libpararealhip.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return binding.load()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(pr_[a-z_0-9]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding knows all of them
+    assert set(names) <= set(binding._SIGS)
+
+
+def test_opts_default(lib):
+    o = binding.default_opts()
+    assert o.nu_f == 0.005 and o.nu_c == 0.1 and o.n_sound == 4
+    assert o.rank_tol == 1e-10 and o.form == binding.PR_FORM_BATCHED
+    assert o.skip_converged == 1 and o.tile_nt == 0 and o.tile_zc == 0
+
+
+def test_strerror(lib):
+    assert lib.pr_strerror(0) == b"ok"
+    assert lib.pr_strerror(-4) == b"unstable propagator"
+    assert lib.pr_strerror(-99) == b"unknown error"
+
+
+def _scan(prm):
+    rf = rg = 0.0
+    for kx in range(prm.nx):
+        for kz in range(prm.nz):
+            Rf = rk3_poly(prm.dt_f * fine_symbol(prm, kx, kz))
+            rf = max(rf, np.abs(np.linalg.eigvals(Rf)).max())
+            rg = max(rg, np.abs(np.linalg.eigvals(
+                coarse_step_symbol(prm, kx, kz))).max())
+    return rf, rg
+
+
+@pytest.mark.parametrize("nx,nz,U,ns", [(32, 16, 0.1, 4), (16, 16, -0.2, 6),
+                                        (24, 12, 0.3, 4), (24, 12, 0.3, 10)])
+def test_stability_scan_matches_symbols(lib, nx, nz, U, ns):
+    prob = W.problem(nx, nz, 4, U=U, n_sound=ns)
+    prm = Params(**prob)
+    want_f, want_g = _scan(prm)
+    got_f, got_g = binding.check_stability(nx, nz, prob["c_s"], U,
+                                           prob["dt_f"], prob["dt_g"],
+                                           n_sound=ns)
+    assert abs(got_f - want_f) < 1e-12
+    assert abs(got_g - want_g) < 1e-12
+
+
+def test_stability_of_workload_rule(lib):
+    """The N_sound rule of the workloads keeps G stable up to U = 0.3 on
+    the 2:1 grids; N_sound = 4 is not enough at U = 0.3."""
+    for U in (0.0, 0.1, 0.15, 0.2, 0.25, 0.3):
+        prob = W.problem(64, 32, 8, U=U)
+        rf, rg = binding.check_stability(64, 32, 1.0, U, prob["dt_f"],
+                                         prob["dt_g"], n_sound=prob["n_sound"])
+        assert rf <= 1 + 1e-12 and rg <= 1 + 1e-12, U
+    prob = W.problem(64, 32, 8, U=0.3, n_sound=4)
+    _, rg = binding.check_stability(64, 32, 1.0, 0.3, prob["dt_f"],
+                                    prob["dt_g"], n_sound=4)
+    assert rg > 1.05
+
+
+def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
+    h = ctypes.c_void_p()
+    o = binding.default_opts(**opts)
+    rc = lib.pr_create_ex(ctypes.byref(binding.grid(nx, nz, T)), c_s, U, dt_f,
+                          dt_g, P, ctypes.byref(o), None, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("kw,why", [
+    (dict(nx=7), "nx and nz must be >= 8"),
+    (dict(nz=4), "nx and nz must be >= 8"),
+    (dict(P=0), "P must be"),
+    (dict(dt_f=0.3 / 64), "dt_f"),
+    (dict(dt_g=0.0), "time steps"),
+    (dict(n_sound=0), "n_sound"),
+    (dict(tile_nt=100), "tile_nt"),
+    (dict(tile_zc=12), "tile_zc"),
+])
+def test_create_rejects_bad_arguments(lib, kw, why):
+    args = dict(nx=64, nz=32, c_s=1.0, U=0.1, dt_f=0.2 / 64, dt_g=2.0 / 64,
+                P=8)
+    opts = {k: kw.pop(k) for k in list(kw) if k in ("n_sound", "tile_nt",
+                                                   "tile_zc")}
+    args.update(kw)
+    rc, h = _create(lib, **args, **opts)
+    assert rc == binding.PR_EINVAL and not h.value
+    assert why in lib.pr_last_error(None).decode()
+
+
+def test_create_rejects_unstable_coarse(lib):
+    prob = W.problem(64, 32, 8, U=0.3, n_sound=4)
+    rc, h = _create(lib, 64, 32, 1.0, 0.3, prob["dt_f"], prob["dt_g"], 8,
+                    n_sound=4)
+    assert rc == binding.PR_EUNSTABLE and not h.value
+
+
+def test_footprint():
+    b = binding.footprint(512, 256, 32, 4)
+    d = 3 * 512 * 256
+    # basis S and D(S) of P*K vectors dominate
+    assert 2 * 32 * 4 * d * 8 < b < 2.2 * (2 * 32 * 4 + 8 * 32) * d * 8
+    assert binding.footprint(64, 32, 8, 0) > 0
