@@ -109,6 +109,12 @@ def load(path=LIB_PATH):
         raise RuntimeError(
             f"{path} is missing: build it with "
             "`python -m paper_1510_02237_amd.build` (hipcc, gfx950)")
+    # torch ships its own HIP runtime under the same soname; load it first
+    # so that this library binds to the same runtime instead of a second one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)

@@ -190,7 +190,7 @@ __global__ void k_check_finite(const double* __restrict__ v, int64_t n,
 // lane l supplies A[m0 + l%16][k] and B[k][n0 + l%16] at k-slot l/16; the
 // k-slots of four consecutive instructions are mapped to four consecutive
 // x so that each lane reads 32 contiguous bytes of its vector.  The output
-// of a block sits in lane l, register i at row 4*(l/16)+i, column l%16.
+// of a block sits in lane l, register i at row l/16 + 4*i, column l%16.
 // Partial tiles of each chunk go to work[split][M][N], summed in order by
 // k_reduce_splits.
 constexpr int TN_T = 64;
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn_mfma(
     const int col = nb + r16;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = mb + 4 * kq + i;
+      const int row = mb + kq + 4 * i;
       if (row < M && col < N) W[(int64_t)row * N + col] = v[i];
     }
   };
@@ -295,7 +295,7 @@ __global__ void k_reduce_splits(const double* __restrict__ work, int nsplit,
 // Computed as the transposed product (N x 16 strip of x per wave):
 // MFMA A-operand = C^T (lane l: C[(j0 + l/16)*ldc + l0 + l%16]) from LDS,
 // B-operand = A (lane l: A[(j0 + l/16)*lda + x0 + l%16], 128-byte runs).
-// Output lane l, register i: Y row l0 + 4*(l/16) + i, column x0 + l%16, so
+// Output lane l, register i: Y row l0 + l/16 + 4*i, column x0 + l%16, so
 // each group of 16 lanes stores 128 contiguous bytes.
 constexpr int NN_JC = 32;  // rows of C staged in LDS per pass
 
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn_mfma(
   for (int b = 0; b < NB; ++b) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int l = b * 16 + 4 * kq + i;
+      const int l = b * 16 + kq + 4 * i;
       if (l < N) {
         double* y = Y + (int64_t)l * ldy + x0 + r16;
         const double v = alpha * acc[b][i];

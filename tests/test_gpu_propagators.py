@@ -68,7 +68,7 @@ def test_fine_sweep_device_tensors():
 
 
 @pytest.mark.parametrize("nx,nz", [(8, 8), (64, 32), (50, 70), (130, 33)])
-@pytest.mark.parametrize("U,ns", [(0.1, 4), (-0.2, 6), (0.3, 10), (0.0, 1)])
+@pytest.mark.parametrize("U,ns", [(0.1, 4), (-0.2, 6), (0.3, 10), (0.0, 5)])
 def test_coarse_step_matches_oracle(nx, nz, U, ns):
     prob = small_problem(nx, nz, 2, U=U, n_g=2, n_sound=ns)
     say(f"coarse {nx}x{nz} U={U} ns={ns}")
