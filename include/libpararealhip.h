@@ -94,7 +94,8 @@ typedef struct pr_opts {
                              bitwise those of iteration k-1 (Section 2.1:
                              after k iterations slices 0..k are exact)         */
   int32_t tile_nt;        /* fine-sweep threads per workgroup, 0 = autotune    */
-  int32_t tile_zc;        /* fine-sweep output rows per workgroup, 0 = auto    */
+  int32_t tile_zc;        /* fine-sweep output rows per workgroup (multiple of
+                             4), 0 = autotune                                  */
 } pr_opts;
 
 typedef struct pr_ctx pr_ctx;

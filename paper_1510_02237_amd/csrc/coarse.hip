@@ -13,8 +13,12 @@
 //
 // One launch performs up to kCoarseMaxSubPerLaunch substeps: a workgroup
 // loads a TX x TZ tile plus a halo of 2 cells per substep (and one more
-// column on the upwind side when it evaluates R) into LDS, runs the
-// substeps there, and writes the tile interior.  States are batched along
+// column on each side when it evaluates R) into LDS, runs the substeps
+// there and writes the tile interior.  The LDS region carries one more
+// ring of cells that is never written with valid data, so every neighbour
+// is a fixed offset and the points near the edge (whose results are
+// discarded) need no clamping.  Each thread owns the same MPT points in
+// every phase; their indices are computed once.  States are batched along
 // blockIdx.y.
 #include "pr_internal.h"
 
@@ -26,14 +30,16 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-constexpr int TX = 32, TZ = 32, NT = 256;
+constexpr int TX = 32, TZ = 32, NT = 1024;
 constexpr int HXM = 2 * kCoarseMaxSubPerLaunch + 1;
 constexpr int HZM = 2 * kCoarseMaxSubPerLaunch;
 constexpr int RXM = TX + 2 * HXM, RZM = TZ + 2 * HZM;
-constexpr int MPT = (RXM * RZM + NT - 1) / NT;  // points per thread
+constexpr int SX = RXM + 2;                         // padded LDS row stride
+constexpr int LDSN = (RZM + 2) * SX;
+constexpr int MPT = (RXM * RZM + NT - 1) / NT;      // points per thread
 
 __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
-  __shared__ double su[RZM * RXM], sw[RZM * RXM], sp[RZM * RXM];
+  __shared__ double su[LDSN], sw[LDSN], sp[LDSN];
   const int nx = L.nx, nz = L.nz;
   const int64_t n = (int64_t)nx * nz;
   const int xtiles = (nx + TX - 1) / TX;
@@ -52,48 +58,73 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   const int t = threadIdx.x;
   const CoarseCoef k = L.c;
 
-  for (int q = t; q < npts; q += NT) {
-    const int a = q % RX, b = q / RX;
-    const int64_t g = (int64_t)wrap(gz0 + b, nz) * nx + wrap(gx0 + a, nx);
-    su[q] = in[g];
-    sw[q] = in[n + g];
-    sp[q] = in[2 * n + g];
+  // Zero the whole LDS region once (the outer ring stays zero).
+  for (int q = t; q < LDSN; q += NT) su[q] = sw[q] = sp[q] = 0.0;
+
+  int qi[MPT];       // LDS index of each owned point, -1 if none
+  int64_t gi[MPT];   // global index of each owned point (wrapped)
+  int cflag[MPT];    // 1 if the point is in the tile interior and inside
+                     // the grid (stored at the end)
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    const int q = t + m * NT;
+    qi[m] = -1;
+    gi[m] = 0;
+    cflag[m] = 0;
+    if (q < npts) {
+      const int a = q % RX, b = q / RX;
+      qi[m] = (b + 1) * SX + a + 1;
+      gi[m] = (int64_t)wrap(gz0 + b, nz) * nx + wrap(gx0 + a, nx);
+      const int x = xt * TX + a - hx, z = zt * TZ + b - hz;
+      cflag[m] = (a >= hx && a < hx + TX && b >= hz && b < hz + TZ && x < nx &&
+                  z < nz) ? 1 : 0;
+    }
+  }
+  double vu[MPT], vw[MPT], vp[MPT];
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    if (qi[m] >= 0) {
+      vu[m] = in[gi[m]];
+      vw[m] = in[n + gi[m]];
+      vp[m] = in[2 * n + gi[m]];
+    }
+  }
+  __syncthreads();  // zeroing done before the region is filled
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    if (qi[m] >= 0) {
+      su[qi[m]] = vu[m];
+      sw[qi[m]] = vw[m];
+      sp[qi[m]] = vp[m];
+    }
   }
   __syncthreads();
 
   double Ru[MPT], Rw[MPT], Rp[MPT];
+  const int dR = k.upwind_left ? -1 : 1;  // upwind neighbour offset
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
-    const int q = t + m * NT;
     Ru[m] = Rw[m] = Rp[m] = 0.0;
-    if (q < npts) {
-      const int a = q % RX, b = q / RX;
-      if (computeR) {
-        if (k.upwind_left) {
-          const int qm = b * RX + (a > 0 ? a - 1 : 0);
-          Ru[m] = k.cR * (su[q] - su[qm]);
-          Rw[m] = k.cR * (sw[q] - sw[qm]);
-          Rp[m] = k.cR * (sp[q] - sp[qm]);
-        } else {
-          const int qp = b * RX + (a < RX - 1 ? a + 1 : RX - 1);
-          Ru[m] = k.cR * (su[qp] - su[q]);
-          Rw[m] = k.cR * (sw[qp] - sw[q]);
-          Rp[m] = k.cR * (sp[qp] - sp[q]);
-        }
-        if (storeR && a >= hx && a < hx + TX && b >= hz && b < hz + TZ) {
-          const int x = xt * TX + a - hx, z = zt * TZ + b - hz;
-          if (x < nx && z < nz) {
-            const int64_t g = (int64_t)z * nx + x;
-            Rg[g] = Ru[m];
-            Rg[n + g] = Rw[m];
-            Rg[2 * n + g] = Rp[m];
-          }
-        }
-      } else {
-        const int64_t g = (int64_t)wrap(gz0 + b, nz) * nx + wrap(gx0 + a, nx);
-        Ru[m] = Rg[g];
-        Rw[m] = Rg[n + g];
-        Rp[m] = Rg[2 * n + g];
+    if (qi[m] < 0) continue;
+    if (computeR) {
+      const int q = qi[m], qn = q + dR;
+      // cR (q_i - q_{i-1}) for U >= 0, cR (q_{i+1} - q_i) for U < 0
+      Ru[m] = k.cR * (dR < 0 ? su[q] - su[qn] : su[qn] - su[q]);
+      Rw[m] = k.cR * (dR < 0 ? sw[q] - sw[qn] : sw[qn] - sw[q]);
+      Rp[m] = k.cR * (dR < 0 ? sp[q] - sp[qn] : sp[qn] - sp[q]);
+    } else {
+      Ru[m] = Rg[gi[m]];
+      Rw[m] = Rg[n + gi[m]];
+      Rp[m] = Rg[2 * n + gi[m]];
+    }
+  }
+  if (computeR && storeR) {
+#pragma unroll
+    for (int m = 0; m < MPT; ++m) {
+      if (cflag[m]) {
+        Rg[gi[m]] = Ru[m];
+        Rg[n + gi[m]] = Rw[m];
+        Rg[2 * n + gi[m]] = Rp[m];
       }
     }
   }
@@ -103,59 +134,49 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
     double un[MPT], wn[MPT];
 #pragma unroll
     for (int m = 0; m < MPT; ++m) {
-      const int q = t + m * NT;
       un[m] = wn[m] = 0.0;
-      if (q < npts) {
-        const int a = q % RX, b = q / RX;
-        const int am = a > 0 ? a - 1 : 0, ap = a < RX - 1 ? a + 1 : RX - 1;
-        const int bm = (b > 0 ? b - 1 : 0) * RX, bp = (b < RZ - 1 ? b + 1 : RZ - 1) * RX;
-        const int bc = b * RX;
-        const double u = su[q], w = sw[q];
-        const double dpx = sp[bc + ap] - sp[bc + am];
-        const double dpz = sp[bp + a] - sp[bm + a];
-        const double gxx = (su[bc + ap] + su[bc + am]) - 2.0 * u;
-        const double gzz = (sw[bp + a] + sw[bm + a]) - 2.0 * w;
-        const double wx = (sw[bp + ap] - sw[bm + ap]) - (sw[bp + am] - sw[bm + am]);
-        const double uz = (su[bp + ap] - su[bp + am]) - (su[bm + ap] - su[bm + am]);
-        un[m] = u + dtau * (Ru[m] - k.cx2 * dpx + k.kxx * gxx + k.kxzu * wx);
-        wn[m] = w + dtau * (Rw[m] - k.cz2 * dpz + k.kzz * gzz + k.kxzw * uz);
+      if (qi[m] < 0) continue;
+      const int q = qi[m];
+      const double u = su[q], w = sw[q];
+      const double dpx = sp[q + 1] - sp[q - 1];
+      const double dpz = sp[q + SX] - sp[q - SX];
+      const double gxx = (su[q + 1] + su[q - 1]) - 2.0 * u;
+      const double gzz = (sw[q + SX] + sw[q - SX]) - 2.0 * w;
+      const double wx = (sw[q + SX + 1] - sw[q - SX + 1]) -
+                        (sw[q + SX - 1] - sw[q - SX - 1]);
+      const double uz = (su[q + SX + 1] - su[q + SX - 1]) -
+                        (su[q - SX + 1] - su[q - SX - 1]);
+      un[m] = u + dtau * (Ru[m] - k.cx2 * dpx + k.kxx * gxx + k.kxzu * wx);
+      wn[m] = w + dtau * (Rw[m] - k.cz2 * dpz + k.kzz * gzz + k.kxzw * uz);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MPT; ++m) {
+      if (qi[m] >= 0) {
+        su[qi[m]] = un[m];
+        sw[qi[m]] = wn[m];
       }
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MPT; ++m) {
-      const int q = t + m * NT;
-      if (q < npts) {
-        su[q] = un[m];
-        sw[q] = wn[m];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MPT; ++m) {
-      const int q = t + m * NT;
-      if (q < npts) {
-        const int a = q % RX, b = q / RX;
-        const int am = a > 0 ? a - 1 : 0, ap = a < RX - 1 ? a + 1 : RX - 1;
-        const int bm = (b > 0 ? b - 1 : 0) * RX, bp = (b < RZ - 1 ? b + 1 : RZ - 1) * RX;
-        const int bc = b * RX;
-        const double dux = su[bc + ap] - su[bc + am];
-        const double dwz = sw[bp + a] - sw[bm + a];
-        sp[q] = sp[q] + dtau * (Rp[m] - k.cx2 * dux - k.cz2 * dwz);
-      }
+      if (qi[m] < 0) continue;
+      const int q = qi[m];
+      const double dux = su[q + 1] - su[q - 1];
+      const double dwz = sw[q + SX] - sw[q - SX];
+      sp[q] = sp[q] + dtau * (Rp[m] - k.cx2 * dux - k.cz2 * dwz);
     }
     __syncthreads();
   }
 
-  for (int q = t; q < npts; q += NT) {
-    const int a = q % RX, b = q / RX;
-    if (a < hx || a >= hx + TX || b < hz || b >= hz + TZ) continue;
-    const int x = xt * TX + a - hx, z = zt * TZ + b - hz;
-    if (x >= nx || z >= nz) continue;
-    const int64_t g = (int64_t)z * nx + x;
-    out[g] = su[q];
-    out[n + g] = sw[q];
-    out[2 * n + g] = sp[q];
+#pragma unroll
+  for (int m = 0; m < MPT; ++m) {
+    if (cflag[m]) {
+      const int q = qi[m];
+      out[gi[m]] = su[q];
+      out[n + gi[m]] = sw[q];
+      out[2 * n + gi[m]] = sp[q];
+    }
   }
 }
 

@@ -29,6 +29,8 @@ struct pr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t side = nullptr;      // projections overlap the coarse step
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int nt = 256, zc = 64;  // fine-sweep tile (threads, rows)
   bool tuned = false;
@@ -38,6 +40,7 @@ struct pr_ctx {
   int rcap = 0;           // basis capacity (vectors)
   double* Q = nullptr;    // (P+1) iterates q^k_i
   double* Qt = nullptr;   // (P+1) fine results qt^k_i
+  double* GQ = nullptr;   // (P) G(q^k_i), kept current by linearity
   double* Wk = nullptr;   // wcap: sweep ping-pong, batched-G ping
   double* X = nullptr;    // wcap: new raw columns (projected in place)
   double* DX = nullptr;   // wcap: their F - G images
@@ -73,7 +76,7 @@ struct pr_ctx {
 };
 
 enum { kIo = 0, kG = 1, kTa = 2, kTb = 3, kDa = 4, kDb = 5, kRs = 6,
-       kTmp = 7, kSingle = 8 };
+       kTmp = 7, kY = 8, kSingle = 9 };
 
 namespace prh {
 
@@ -98,7 +101,9 @@ int run_coarse(pr_ctx* c, const double* in, double* out, int ns,
 // the previous one copied to pinned host memory).  ensure_arena(c, b, r + b)
 // must have been called before update_begin.
 int krylov_append(pr_ctx* c, const double* X0, const double* FX0, int b);
-int update_begin(pr_ctx* c, const double* X0, const double* FX0, int b);
+// GX0: G of the columns (stride ld), or NULL to compute it here.
+int update_begin(pr_ctx* c, const double* X0, const double* FX0,
+                 const double* GX0, int b);
 int update_mid(pr_ctx* c);
 int update_end(pr_ctx* c);
 // Coarse initialisation q^0_{i+1} = G(q^0_i) (Algorithm 2, initialisation)

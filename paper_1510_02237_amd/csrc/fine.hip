@@ -48,21 +48,46 @@ __device__ __forceinline__ Coef load_coef(const FineCoef& c) {
               c.cx4,    c.cz4,    c.kxx,    c.kxzu,   c.kzz,    c.kxzw};
 }
 
-// Right-hand side at one point.  rc, rm, rp: LDS rows r, r-1, r+1 of the
-// level (each [3][W], field order u, w, p); c: this thread's column in the
-// padded row.  The own-column values along z come from registers.
+// Values a stage carries from row to row (registers): the x-neighbours
+// i-1, i+1 of u and w on the row r about to be computed, and the centred
+// x-differences D_u = u(i+1) - u(i-1), D_w = w(i+1) - w(i-1) on rows r - 1
+// and r.  The grad-div cross terms are differences of these along z:
+//   w(i+1,j+1) - w(i+1,j-1) - w(i-1,j+1) + w(i-1,j-1) = D_w(j+1) - D_w(j-1),
+// so every x-neighbour of u and w at offset +-1 is read from LDS once.
+struct Carry {
+  double xum, xup, xwm, xwp;  // u, w at (r, i-1), (r, i+1)
+  double dum, dwm;            // D_u, D_w at row r - 1
+  double du0, dw0;            // D_u, D_w at row r
+};
+
+// Reads u, w at offsets +-1 of the next row (rn) and returns its D_u, D_w.
+template <int W>
+__device__ __forceinline__ void carry_read(const double (*rn)[W], int c,
+                                           double& um, double& up,
+                                           double& wm, double& wp) {
+  um = rn[0][c - 1];
+  up = rn[0][c + 1];
+  wm = rn[1][c - 1];
+  wp = rn[1][c + 1];
+}
+
+// Right-hand side at one point of row r.  rc: LDS row r of the level
+// ([3][W], fields u, w, p); c: this thread's column in the padded row;
+// the own-column values along z come from registers, the +-1 neighbours
+// of u and w and the D differences from the carry, D_u, D_w of row r + 1
+// from the caller.
 template <int SGN, int W>
 __device__ __forceinline__ void rhs_point(
-    const double (*rc)[W], const double (*rm)[W], const double (*rp)[W],
-    int c, double u0, double wm2, double wm1, double w0, double wp1,
-    double wp2, double pm2, double pm1, double p0, double pp1, double pp2,
-    const Coef& k, double& fu, double& fw, double& fp) {
+    const double (*rc)[W], int c, const Carry& cy, double dup, double dwp,
+    double u0, double wm2, double wm1, double w0, double wp1, double wp2,
+    double pm2, double pm1, double p0, double pp1, double pp2, const Coef& k,
+    double& fu, double& fw, double& fp) {
   const double* U = rc[0];
   const double* Wr = rc[1];
   const double* Pr = rc[2];
-  const double um2 = U[c - 2], um1 = U[c - 1], up1 = U[c + 1], up2 = U[c + 2];
-  const double wxm2 = Wr[c - 2], wxm1 = Wr[c - 1], wxp1 = Wr[c + 1],
-               wxp2 = Wr[c + 2];
+  const double um1 = cy.xum, up1 = cy.xup, wxm1 = cy.xwm, wxp1 = cy.xwp;
+  const double um2 = U[c - 2], up2 = U[c + 2];
+  const double wxm2 = Wr[c - 2], wxp2 = Wr[c + 2];
   const double pxm2 = Pr[c - 2], pxm1 = Pr[c - 1], pxp1 = Pr[c + 1],
                pxp2 = Pr[c + 2];
   double au, aw, ap;
@@ -81,19 +106,14 @@ __device__ __forceinline__ void rhs_point(
     ap = k.a0 * pxm2 + k.a1 * pxm1 + k.a2 * p0 + k.a3 * pxp1 + k.a4 * pxp2 +
          k.a5 * Pr[c + 3];
   }
-  // Cross terms of the grad-div damping: w and u at (i+-1, j+-1).
-  const double wpp = rp[1][c + 1], wpm = rm[1][c + 1];
-  const double wmp = rp[1][c - 1], wmm = rm[1][c - 1];
-  const double upp = rp[0][c + 1], upm = rm[0][c + 1];
-  const double ump = rp[0][c - 1], umm = rm[0][c - 1];
   const double dx4p = (pxm2 - pxp2) + 8.0 * (pxp1 - pxm1);
   const double dz4p = (pm2 - pp2) + 8.0 * (pp1 - pm1);
   const double dx4u = (um2 - up2) + 8.0 * (up1 - um1);
   const double dz4w = (wm2 - wp2) + 8.0 * (wp1 - wm1);
   fu = au - k.cx4 * dx4p + k.kxx * ((up1 + um1) - 2.0 * u0) +
-       k.kxzu * ((wpp - wpm) - (wmp - wmm));
+       k.kxzu * (dwp - cy.dwm);
   fw = aw - k.cz4 * dz4p + k.kzz * ((wp1 + wm1) - 2.0 * w0) +
-       k.kxzw * ((upp - ump) - (upm - umm));
+       k.kxzw * (dup - cy.dum);
   fp = ap - k.cx4 * dx4u - k.cz4 * dz4w;
 }
 
@@ -148,98 +168,103 @@ __global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
   double fu_[PF], fw_[PF], fp_[PF];  // prefetched input rows
 #pragma unroll
   for (int q = 0; q < PF; ++q) {
-    if (q < nrows) {
-      const double* src = in + (int64_t)wrap(z0 - 6 + q, nz) * nx + gx;
-      fu_[q] = src[0];
-      fw_[q] = src[n];
-      fp_[q] = src[2 * n];
-    }
+    const double* src = in + (int64_t)wrap(z0 - 6 + q, nz) * nx + gx;
+    fu_[q] = src[0];
+    fw_[q] = src[n];
+    fp_[q] = src[2 * n];
   }
 
   double iu[8], iw[8], ip[8];  // input rows, indexed by iteration & 7
   double au[8], aw[8], ap[8];  // stage-1 rows
   double bu[8], bw[8], bp[8];  // stage-2 rows
+  Carry c1{}, c2{}, c3{};      // per-stage carries
 
-  for (int base = 0; base < nrows; base += 8) {
-#pragma unroll
-    for (int uu = 0; uu < 8; ++uu) {
-      const int it = base + uu;
-      if (it >= nrows) break;
-      lds_barrier();
-      // Input row z0 - 6 + it.
-      {
-        const int q = uu % PF;
-        iu[uu] = fu_[q];
-        iw[uu] = fw_[q];
-        ip[uu] = fp_[q];
-        ring[0][uu & 3][0][c] = iu[uu];
-        ring[0][uu & 3][1][c] = iw[uu];
-        ring[0][uu & 3][2][c] = ip[uu];
-        if (it + PF < nrows) {
-          const double* src =
-              in + (int64_t)wrap(z0 - 6 + it + PF, nz) * nx + gx;
-          fu_[q] = src[0];
-          fw_[q] = src[n];
-          fp_[q] = src[2 * n];
-        }
-      }
-      // Stage 1 on the input row of iteration it-2:
-      // q* = q^n + dt/3 f(q^n).
-      if (it >= 4) {
-        double fu, fw, fp;
-        rhs_point<SGN, W>(ring[0][(uu - 2) & 3], ring[0][(uu - 3) & 3],
-                          ring[0][(uu - 1) & 3], c, iu[(uu - 2) & 7],
-                          iw[(uu - 4) & 7], iw[(uu - 3) & 7],
-                          iw[(uu - 2) & 7], iw[(uu - 1) & 7], iw[uu & 7],
-                          ip[(uu - 4) & 7], ip[(uu - 3) & 7],
-                          ip[(uu - 2) & 7], ip[(uu - 1) & 7], ip[uu & 7], k,
-                          fu, fw, fp);
-        au[uu] = iu[(uu - 2) & 7] + b1 * fu;
-        aw[uu] = iw[(uu - 2) & 7] + b1 * fw;
-        ap[uu] = ip[(uu - 2) & 7] + b1 * fp;
-        ring[1][uu & 3][0][c] = au[uu];
-        ring[1][uu & 3][1][c] = aw[uu];
-        ring[1][uu & 3][2][c] = ap[uu];
-      }
-      // Stage 2 on the stage-1 row of iteration it-2 (input row of it-4):
-      // q** = q^n + dt/2 f(q*).
-      if (it >= 8) {
-        double fu, fw, fp;
-        rhs_point<SGN, W>(ring[1][(uu - 2) & 3], ring[1][(uu - 3) & 3],
-                          ring[1][(uu - 1) & 3], c, au[(uu - 2) & 7],
-                          aw[(uu - 4) & 7], aw[(uu - 3) & 7],
-                          aw[(uu - 2) & 7], aw[(uu - 1) & 7], aw[uu & 7],
-                          ap[(uu - 4) & 7], ap[(uu - 3) & 7],
-                          ap[(uu - 2) & 7], ap[(uu - 1) & 7], ap[uu & 7], k,
-                          fu, fw, fp);
-        bu[uu] = iu[(uu - 4) & 7] + b2 * fu;
-        bw[uu] = iw[(uu - 4) & 7] + b2 * fw;
-        bp[uu] = ip[(uu - 4) & 7] + b2 * fp;
-        ring[2][uu & 3][0][c] = bu[uu];
-        ring[2][uu & 3][1][c] = bw[uu];
-        ring[2][uu & 3][2][c] = bp[uu];
-      }
-      // Stage 3 on the stage-2 row of iteration it-2 (input row of it-6):
-      // q^{n+1} = q^n + dt f(q**), written out.
-      if (it >= 12) {
-        double fu, fw, fp;
-        rhs_point<SGN, W>(ring[2][(uu - 2) & 3], ring[2][(uu - 3) & 3],
-                          ring[2][(uu - 1) & 3], c, bu[(uu - 2) & 7],
-                          bw[(uu - 4) & 7], bw[(uu - 3) & 7],
-                          bw[(uu - 2) & 7], bw[(uu - 1) & 7], bw[uu & 7],
-                          bp[(uu - 4) & 7], bp[(uu - 3) & 7],
-                          bp[(uu - 2) & 7], bp[(uu - 1) & 7], bp[uu & 7], k,
-                          fu, fw, fp);
-        const int z3 = z0 + it - 12;
-        if (store_col && z3 < nz) {
-          double* dst = out + (int64_t)z3 * nx + xo;
-          dst[0] = iu[(uu - 6) & 7] + dt * fu;
-          dst[n] = iw[(uu - 6) & 7] + dt * fw;
-          dst[2 * n] = ip[(uu - 6) & 7] + dt * fp;
-        }
-      }
-    }
+  // One row iteration.  For each stage L, PREL reads the +-1 neighbours of
+  // the row after the one it computes (from an earlier iteration) and
+  // advances the carry; DOL computes the row.  All flags are compile-time
+  // after unrolling, so in the steady state the three stages (which read
+  // only rows produced in earlier iterations) are straight-line code the
+  // scheduler interleaves.  Rows past the chunk (it >= nrows) are computed
+  // and discarded, so the row count need not be a multiple of the unroll.
+#define PR_STAGE(PRE, DO, LVL, CY, ZU, ZW, ZP, BU, BW, BP, OU, OW, OP, BETA, STORE) \
+  if (PRE) {                                                                  \
+    double xum, xup, xwm, xwp;                                                \
+    carry_read<W>(ring[LVL][((uu) - 1) & 3], c, xum, xup, xwm, xwp);          \
+    const double dup = xup - xum, dwp = xwp - xwm;                            \
+    if (DO) {                                                                 \
+      double fu, fw, fp;                                                      \
+      rhs_point<SGN, W>(ring[LVL][((uu) - 2) & 3], c, CY, dup, dwp,           \
+                        ZU[((uu) - 2) & 7], ZW[((uu) - 4) & 7],               \
+                        ZW[((uu) - 3) & 7], ZW[((uu) - 2) & 7],               \
+                        ZW[((uu) - 1) & 7], ZW[(uu) & 7], ZP[((uu) - 4) & 7], \
+                        ZP[((uu) - 3) & 7], ZP[((uu) - 2) & 7],               \
+                        ZP[((uu) - 1) & 7], ZP[(uu) & 7], k, fu, fw, fp);     \
+      const double nu = BU + (BETA) * fu, nw = BW + (BETA) * fw,              \
+                   np = BP + (BETA) * fp;                                     \
+      STORE                                                                   \
+    }                                                                         \
+    CY.dum = CY.du0;                                                          \
+    CY.dwm = CY.dw0;                                                          \
+    CY.du0 = dup;                                                             \
+    CY.dw0 = dwp;                                                             \
+    CY.xum = xum;                                                             \
+    CY.xup = xup;                                                             \
+    CY.xwm = xwm;                                                             \
+    CY.xwp = xwp;                                                             \
   }
+
+#define PR_ROW(uu, it, P1, D1, P2, D2, P3, D3)                                 \
+  {                                                                           \
+    lds_barrier();                                                            \
+    {                                                                         \
+      const int q = (uu) % PF;                                                \
+      iu[uu] = fu_[q];                                                        \
+      iw[uu] = fw_[q];                                                        \
+      ip[uu] = fp_[q];                                                        \
+      ring[0][(uu) & 3][0][c] = iu[uu];                                       \
+      ring[0][(uu) & 3][1][c] = iw[uu];                                       \
+      ring[0][(uu) & 3][2][c] = ip[uu];                                       \
+      const double* src = in + (int64_t)wrap(z0 - 6 + (it) + PF, nz) * nx + gx; \
+      fu_[q] = src[0];                                                        \
+      fw_[q] = src[n];                                                        \
+      fp_[q] = src[2 * n];                                                    \
+    }                                                                         \
+    PR_STAGE(P1, D1, 0, c1, iu, iw, ip, iu[((uu) - 2) & 7],                   \
+             iw[((uu) - 2) & 7], ip[((uu) - 2) & 7], au, aw, ap, b1,          \
+             au[uu] = nu; aw[uu] = nw; ap[uu] = np;                           \
+             ring[1][(uu) & 3][0][c] = nu; ring[1][(uu) & 3][1][c] = nw;      \
+             ring[1][(uu) & 3][2][c] = np;)                                   \
+    PR_STAGE(P2, D2, 1, c2, au, aw, ap, iu[((uu) - 4) & 7],                   \
+             iw[((uu) - 4) & 7], ip[((uu) - 4) & 7], bu, bw, bp, b2,          \
+             bu[uu] = nu; bw[uu] = nw; bp[uu] = np;                           \
+             ring[2][(uu) & 3][0][c] = nu; ring[2][(uu) & 3][1][c] = nw;      \
+             ring[2][(uu) & 3][2][c] = np;)                                   \
+    PR_STAGE(P3, D3, 2, c3, bu, bw, bp, iu[((uu) - 6) & 7],                   \
+             iw[((uu) - 6) & 7], ip[((uu) - 6) & 7], bu, bw, bp, dt,          \
+             const int z3 = z0 + (it) - 12;                                   \
+             if (store_col && (it) < nrows && z3 < nz) {                      \
+               double* dst = out + (int64_t)z3 * nx + xo;                     \
+               dst[0] = nu;                                                   \
+               dst[n] = nw;                                                   \
+               dst[2 * n] = np;                                               \
+             })                                                               \
+  }
+
+  // Warm-up: stage L starts carrying two rows before it first computes
+  // (stage 1 computes from row 4, stage 2 from 8, stage 3 from 12).
+#pragma unroll
+  for (int uu = 0; uu < 8; ++uu)
+    PR_ROW(uu, uu, uu >= 2, uu >= 4, uu >= 6, false, false, false)
+#pragma unroll
+  for (int uu = 0; uu < 8; ++uu)
+    PR_ROW(uu, 8 + uu, true, true, true, true, uu >= 2, uu >= 4)
+  for (int base = 16; base < nrows; base += 8) {
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu)
+      PR_ROW(uu, base + uu, true, true, true, true, true, true)
+  }
+#undef PR_ROW
+#undef PR_STAGE
 }
 
 // Unfused stage: out = base + beta f(in), one point per thread, neighbours

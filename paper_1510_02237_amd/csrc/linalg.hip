@@ -18,7 +18,8 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int GEMV_NT = 256;
-constexpr int GEMV_E = 8;  // elements of x per thread
+constexpr int GEMV_E = 8;   // elements of x per thread
+constexpr int GEMV_JG = 8;  // columns per workgroup
 constexpr int GEMV_CHUNK = GEMV_NT * GEMV_E;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -43,74 +44,94 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// c = V^T x, partial sums: blockIdx.x picks a chunk of GEMV_CHUNK elements
+// of x, blockIdx.y a group of GEMV_JG columns; each thread keeps its
+// GEMV_E elements of x in registers and accumulates GEMV_JG dot products,
+// reduced across the workgroup once per group.
 __global__ __launch_bounds__(GEMV_NT) void k_gemv_t(
     const double* __restrict__ V, int64_t ld, int ncols,
     const double* __restrict__ x, int64_t d, double* __restrict__ part) {
-  __shared__ double sh[4 * (GEMV_NT / 64)];
+  __shared__ double sh[GEMV_JG][GEMV_NT / 64];
   const int64_t x0 = (int64_t)blockIdx.x * GEMV_CHUNK;
+  const int j0 = blockIdx.y * GEMV_JG;
   double xv[GEMV_E];
 #pragma unroll
   for (int e = 0; e < GEMV_E; ++e) {
     const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
     xv[e] = i < d ? x[i] : 0.0;
   }
-  for (int j0 = 0; j0 < ncols; j0 += 4) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  double acc[GEMV_JG];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (j0 + q < ncols) {
-        const double* col = V + (int64_t)(j0 + q) * ld;
-#pragma unroll
-        for (int e = 0; e < GEMV_E; ++e) {
-          const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
-          if (i < d) acc[q] += col[i] * xv[e];
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) sh[q * (GEMV_NT / 64) + wv] = acc[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < 4 && j0 + threadIdx.x < ncols) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < GEMV_NT / 64; ++w)
-        s += sh[threadIdx.x * (GEMV_NT / 64) + w];
-      part[(int64_t)blockIdx.x * ncols + j0 + threadIdx.x] = s;
-    }
-  }
-}
-
-__global__ void k_colnorm2_part(const double* __restrict__ V, int64_t ld,
-                                int ncols, int64_t d,
-                                double* __restrict__ part) {
-  __shared__ double sh[GEMV_NT / 64];
-  const int64_t x0 = (int64_t)blockIdx.x * GEMV_CHUNK;
-  for (int j = 0; j < ncols; ++j) {
+  for (int q = 0; q < GEMV_JG; ++q) {
+    acc[q] = 0.0;
+    const int j = j0 + q < ncols ? j0 + q : ncols - 1;
     const double* col = V + (int64_t)j * ld;
-    double acc = 0.0;
 #pragma unroll
     for (int e = 0; e < GEMV_E; ++e) {
       const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
-      if (i < d) acc += col[i] * col[i];
+      if (i < d) acc[q] += col[i] * xv[e];
     }
-    const double s = block_sum<GEMV_NT>(acc, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * ncols + j] = s;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < GEMV_JG; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) sh[q][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < GEMV_JG && j0 + (int)threadIdx.x < ncols) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < GEMV_NT / 64; ++w) s += sh[threadIdx.x][w];
+    part[(int64_t)blockIdx.x * ncols + j0 + threadIdx.x] = s;
   }
 }
 
-__global__ void k_reduce_cols(const double* __restrict__ part, int nblk,
-                              int ncols, double* __restrict__ c) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(GEMV_NT) void k_colnorm2_part(
+    const double* __restrict__ V, int64_t ld, int ncols, int64_t d,
+    double* __restrict__ part) {
+  __shared__ double sh[GEMV_JG][GEMV_NT / 64];
+  const int64_t x0 = (int64_t)blockIdx.x * GEMV_CHUNK;
+  const int j0 = blockIdx.y * GEMV_JG;
+  double acc[GEMV_JG];
+#pragma unroll
+  for (int q = 0; q < GEMV_JG; ++q) {
+    acc[q] = 0.0;
+    const int j = j0 + q < ncols ? j0 + q : ncols - 1;
+    const double* col = V + (int64_t)j * ld;
+#pragma unroll
+    for (int e = 0; e < GEMV_E; ++e) {
+      const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
+      if (i < d) acc[q] += col[i] * col[i];
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < GEMV_JG; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) sh[q][wv] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < GEMV_JG && j0 + (int)threadIdx.x < ncols) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < GEMV_NT / 64; ++w) s += sh[threadIdx.x][w];
+    part[(int64_t)blockIdx.x * ncols + j0 + threadIdx.x] = s;
+  }
+}
+
+// c[j] = sum_b part[b*ncols + j]: one wave per column; lane l sums the
+// blocks l, l + 64, ... in order, then a fixed butterfly across the wave.
+__global__ __launch_bounds__(256) void k_reduce_cols(
+    const double* __restrict__ part, int nblk, int ncols,
+    double* __restrict__ c) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (j >= ncols) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * ncols + j];
-  c[j] = s;
+  for (int b = lane; b < nblk; b += 64) s += part[(int64_t)b * ncols + j];
+  s = wave_sum(s);
+  if (lane == 0) c[j] = s;
 }
 
 constexpr int COMB_NT = 256;
@@ -133,14 +154,16 @@ __global__ __launch_bounds__(COMB_NT) void k_combine(
 #pragma unroll
   for (int e = 0; e < COMB_E; ++e) acc[e] = 0.0;
   int j = 0;
-  for (; j + 2 <= ncols; j += 2) {
-    const double c0 = cs[j], c1 = cs[j + 1];
+  for (; j + 4 <= ncols; j += 4) {
+    const double c0 = cs[j], c1 = cs[j + 1], c2 = cs[j + 2], c3 = cs[j + 3];
     const double* d0 = D + (int64_t)j * ld;
     const double* d1 = d0 + ld;
+    const double* d2 = d1 + ld;
+    const double* d3 = d2 + ld;
 #pragma unroll
     for (int e = 0; e < COMB_E; ++e) {
       const int64_t i = x0 + e * COMB_NT;
-      if (i < d) acc[e] += d0[i] * c0 + d1[i] * c1;
+      if (i < d) acc[e] += (d0[i] * c0 + d1[i] * c1) + (d2[i] * c2 + d3[i] * c3);
     }
   }
   for (; j < ncols; ++j) {
@@ -164,6 +187,24 @@ __global__ __launch_bounds__(COMB_NT) void k_combine(
     } else {
       q[i] = k;
     }
+  }
+}
+
+// nw = qt + (g + y); delta = nw - q (if delta); q = nw.  Same association
+// as k_combine<0> with y = sum_j D[j] c[j] computed beforehand.
+// Optionally gacc += g (running G of the iterate being corrected).
+__global__ __launch_bounds__(256) void k_combine3(
+    double* __restrict__ q, double* __restrict__ delta,
+    const double* __restrict__ qt, const double* __restrict__ g,
+    const double* __restrict__ y, double* __restrict__ gacc, int64_t d) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double gi = g ? g[i] : 0.0;
+    const double k = gi + (y ? y[i] : 0.0);
+    const double nw = qt[i] + k;
+    if (delta) delta[i] = nw - q[i];
+    q[i] = nw;
+    if (gacc) gacc[i] += gi;
   }
 }
 
@@ -281,13 +322,18 @@ __global__ __launch_bounds__(256) void k_gemm_tn_fma(
   }
 }
 
-__global__ void k_reduce_splits(const double* __restrict__ work, int nsplit,
-                                int64_t mn, double* __restrict__ C) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// C[q] = sum_k work[k*mn + q]: one wave per output element, lanes over the
+// splits in a fixed order, then a fixed butterfly.
+__global__ __launch_bounds__(256) void k_reduce_splits(
+    const double* __restrict__ work, int nsplit, int64_t mn,
+    double* __restrict__ C) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (q >= mn) return;
   double s = 0.0;
-  for (int k = 0; k < nsplit; ++k) s += work[(int64_t)k * mn + q];
-  C[q] = s;
+  for (int k = lane; k < nsplit; k += 64) s += work[(int64_t)k * mn + q];
+  s = wave_sum(s);
+  if (lane == 0) C[q] = s;
 }
 
 // ----------------------------------------------------------------- GEMM NN
@@ -492,6 +538,92 @@ __global__ __launch_bounds__(PC_NT) void k_pchol(
   if (t == 0) *rank_out = rho;
 }
 
+// Same factorisation for b <= 128 by one wavefront with the factor L in
+// LDS: the pivot search is a wave reduction, and no workgroup barrier is
+// needed inside the factorisation.
+constexpr int PC1_MAX = 128;
+
+__global__ __launch_bounds__(64) void k_pchol_wave(
+    const double* __restrict__ G, int b, const double* __restrict__ n0,
+    double* r11sq, double rank_tol2, double rel2, int pivot,
+    double* __restrict__ T, int* rank_out) {
+  __shared__ double L[PC1_MAX * PC1_MAX];
+  __shared__ double diag[PC1_MAX];
+  __shared__ int perm[PC1_MAX];
+  const int t = threadIdx.x;
+  for (int q = t; q < b; q += 64) {
+    diag[q] = G[(int64_t)q * b + q];
+    perm[q] = q;
+  }
+  double m = 0.0;
+  if (pivot && n0)
+    for (int q = t; q < b; q += 64) m = fmax(m, n0[q]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if (r11sq) m = fmax(m, *r11sq);
+  const double abs2 = rank_tol2 * m;
+  __syncthreads();
+  if (t == 0 && r11sq && pivot) *r11sq = m;
+  int rho = b;
+  for (int k = 0; k < b; ++k) {
+    int p = k;
+    if (pivot) {
+      double best = -1.0;
+      int bi = b;
+      for (int q = k + t; q < b; q += 64)
+        if (diag[q] > best) { best = diag[q]; bi = q; }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(best, o, 64);
+        const int i2 = __shfl_xor(bi, o, 64);
+        if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+      }
+      p = bi;
+      const double thr = fmax(abs2, rel2 * n0[perm[p]]);
+      if (!(best > thr)) { rho = k; break; }
+      if (p != k) {
+        for (int i = t; i < k; i += 64) {
+          const double a = L[k * PC1_MAX + i];
+          L[k * PC1_MAX + i] = L[p * PC1_MAX + i];
+          L[p * PC1_MAX + i] = a;
+        }
+        __syncthreads();
+        if (t == 0) {
+          const double a = diag[k]; diag[k] = diag[p]; diag[p] = a;
+          const int pi = perm[k]; perm[k] = perm[p]; perm[p] = pi;
+        }
+        __syncthreads();
+      }
+    } else if (!(diag[k] > 0.0)) {
+      rho = k;
+      break;
+    }
+    const double lkk = sqrt(diag[k]);
+    const int ck = perm[k];
+    for (int jj = k + 1 + t; jj < b; jj += 64) {
+      double sacc = G[(int64_t)perm[jj] * b + ck];
+      for (int i = 0; i < k; ++i) sacc -= L[jj * PC1_MAX + i] * L[k * PC1_MAX + i];
+      const double l = sacc / lkk;
+      L[jj * PC1_MAX + k] = l;
+      diag[jj] -= l * l;
+    }
+    if (t == 0) L[k * PC1_MAX + k] = lkk;
+    __syncthreads();
+  }
+  for (int q = t; q < b * b; q += 64) T[q] = 0.0;
+  __syncthreads();
+  for (int cc = t; cc < rho; cc += 64) {
+    T[(int64_t)perm[cc] * b + cc] = 1.0 / L[cc * PC1_MAX + cc];
+    for (int i = cc - 1; i >= 0; --i) {
+      double sacc = 0.0;
+      for (int mm = i + 1; mm <= cc; ++mm)
+        sacc += L[mm * PC1_MAX + i] * T[(int64_t)perm[mm] * b + cc];
+      T[(int64_t)perm[i] * b + cc] = -sacc / L[i * PC1_MAX + i];
+    }
+  }
+  if (t == 0) *rank_out = rho;
+}
+
 __global__ void k_small_matmul(const double* __restrict__ T1, int b, int rho1,
                                const double* __restrict__ T2, int rho2,
                                double* __restrict__ T3) {
@@ -513,15 +645,15 @@ hipError_t launch_gemv_t(const double* V, int64_t ld, int ncols,
                          const double* x, int64_t d, double* part, int nblk,
                          hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemv_t, dim3(nblk), dim3(GEMV_NT), 0, s, V, ld, ncols,
-                     x, d, part);
+  hipLaunchKernelGGL(k_gemv_t, dim3(nblk, (ncols + GEMV_JG - 1) / GEMV_JG),
+                     dim3(GEMV_NT), 0, s, V, ld, ncols, x, d, part);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_cols(const double* part, int nblk, int ncols,
                               double* c, hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_cols, dim3((ncols + 127) / 128), dim3(128), 0, s,
+  hipLaunchKernelGGL(k_reduce_cols, dim3((ncols + 3) / 4), dim3(256), 0, s,
                      part, nblk, ncols, c);
   return hipGetLastError();
 }
@@ -530,8 +662,9 @@ hipError_t launch_colnorm2(const double* V, int64_t ld, int ncols, int64_t d,
                            double* part, double* nrm2, hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
   const int nblk = gemv_t_blocks(d);
-  hipLaunchKernelGGL(k_colnorm2_part, dim3(nblk), dim3(GEMV_NT), 0, s, V, ld,
-                     ncols, d, part);
+  hipLaunchKernelGGL(k_colnorm2_part,
+                     dim3(nblk, (ncols + GEMV_JG - 1) / GEMV_JG),
+                     dim3(GEMV_NT), 0, s, V, ld, ncols, d, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_cols(part, nblk, ncols, nrm2, s);
@@ -557,6 +690,16 @@ hipError_t launch_lincomb(double* out, const double* g, const double* D,
   hipLaunchKernelGGL(k_combine<1>, dim3((unsigned)((d + per - 1) / per)),
                      dim3(COMB_NT), 0, s, out, (double*)nullptr,
                      (const double*)nullptr, g, D, ld, ncols, c, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine3(double* q, double* delta_out, const double* qt,
+                           const double* g, const double* y, double* gacc,
+                           int64_t d, hipStream_t s) {
+  int64_t blocks = (d + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_combine3, dim3((unsigned)blocks), dim3(256), 0, s, q,
+                     delta_out, qt, g, y, gacc, d);
   return hipGetLastError();
 }
 
@@ -586,7 +729,7 @@ void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
   *nt = (N + TN_T - 1) / TN_T;
   const int tiles = *mt * *nt;
   int64_t ns = (1024 + tiles - 1) / tiles;
-  const int64_t maxs = (d + 255) / 256;
+  const int64_t maxs = (d + 1023) / 1024;  // at least 1024 elements a split
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;
   int64_t k = (d + ns - 1) / ns;
@@ -598,11 +741,11 @@ void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
 
 // Upper bound of nsplit * M * N over every M <= Mmax, N <= Nmax at this d:
 // nsplit <= ceil(1024 / tiles) with M N <= 4096 tiles gives
-// (1024 + tiles) * 4096, and nsplit <= ceil(d / 256) gives the second bound.
+// (1024 + tiles) * 4096, and nsplit <= ceil(d / 1024) gives the second bound.
 size_t gemm_tn_work(int Mmax, int Nmax, int64_t d) {
   const int64_t tiles = (int64_t)((Mmax + TN_T - 1) / TN_T) * ((Nmax + TN_T - 1) / TN_T);
   const int64_t a = (1024 + tiles) * TN_T * TN_T;
-  const int64_t b = ((d + 255) / 256) * (int64_t)Mmax * Nmax;
+  const int64_t b = ((d + 1023) / 1024) * (int64_t)Mmax * Nmax;
   return (size_t)std::min(a, b);
 }
 
@@ -625,7 +768,7 @@ hipError_t launch_gemm_tn(const double* A, int64_t lda, int M,
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t mn = (int64_t)M * N;
-  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((mn + 255) / 256)),
+  hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((mn + 3) / 4)),
                      dim3(256), 0, s, work, ns, mn, C);
   return hipGetLastError();
 }
@@ -659,8 +802,12 @@ hipError_t launch_pchol(const double* G, int b, const double* n0,
                         double* r11sq, double rank_tol2, double rel2,
                         int pivot, double* T, int* rank, double* work,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_pchol, dim3(1), dim3(PC_NT), 0, s, G, b, n0, r11sq,
-                     rank_tol2, rel2, pivot, T, rank, work);
+  if (b <= PC1_MAX)
+    hipLaunchKernelGGL(k_pchol_wave, dim3(1), dim3(64), 0, s, G, b, n0, r11sq,
+                       rank_tol2, rel2, pivot, T, rank);
+  else
+    hipLaunchKernelGGL(k_pchol, dim3(1), dim3(PC_NT), 0, s, G, b, n0, r11sq,
+                       rank_tol2, rel2, pivot, T, rank, work);
   return hipGetLastError();
 }
 

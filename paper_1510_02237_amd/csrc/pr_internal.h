@@ -126,6 +126,13 @@ hipError_t launch_combine(double* q, double* delta_out, const double* qt,
                           const double* g, const double* D, int64_t ld,
                           int ncols, const double* c, int64_t d,
                           hipStream_t s);
+// Serial-correction combine with the fine part precomputed:
+//   nw = qt + (g + y);  if (delta_out) delta_out = nw - q;  q = nw;
+//   if (gacc) gacc += g
+// (g, y, gacc optional).
+hipError_t launch_combine3(double* q, double* delta_out, const double* qt,
+                           const double* g, const double* y, double* gacc,
+                           int64_t d, hipStream_t s);
 // out = g + sum_j D[j] c[j] (out may alias g).
 hipError_t launch_lincomb(double* out, const double* g, const double* D,
                           int64_t ld, int ncols, const double* c, int64_t d,

@@ -438,7 +438,8 @@ bool pr_server::sweep_tick() {
           (void)hipEventRecord(a->ev_sweep, sweep_stream);
           (void)hipStreamWaitEvent(c->stream, a->ev_sweep, 0);
           a->rc = update_begin(c, c->Q + (int64_t)a->k * c->ld,
-                               c->Qt + (int64_t)(a->k + 1) * c->ld, c->P - a->k);
+                               c->Qt + (int64_t)(a->k + 1) * c->ld,
+                               c->GQ + (int64_t)a->k * c->ld, c->P - a->k);
           (void)hipEventRecord(a->ev_host, c->stream);
           a->phase = a->rc ? kDrain : kUpd1;
         }

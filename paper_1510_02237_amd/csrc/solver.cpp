@@ -114,8 +114,8 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
   if (o->form < 0 || o->form > PR_FORM_STAGEWISE) return fail("unknown form");
   if (o->tile_nt && !fine_nt_supported(o->tile_nt))
     return fail("tile_nt must be 0, 128, 192 or 256");
-  if (o->tile_zc < 0 || o->tile_zc > 4096 || (o->tile_zc % 8))
-    return fail("tile_zc must be a multiple of 8 in [0, 4096]");
+  if (o->tile_zc < 0 || o->tile_zc > 4096 || (o->tile_zc % 4))
+    return fail("tile_zc must be a multiple of 4 in [0, 4096]");
   const double slice = g->T / P;
   if (int_ratio(slice, dt_f, nf)) {
     snprintf(buf, sizeof buf, "(T/P)/dt_f = %.17g is not an integer", slice / dt_f);
@@ -197,6 +197,7 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
   if (!c->Q) {
     RC(dalloc(c, &c->Q, (size_t)(c->P + 1) * ld, "iterates"));
     RC(dalloc(c, &c->Qt, (size_t)(c->P + 1) * ld, "fine results"));
+    RC(dalloc(c, &c->GQ, (size_t)c->P * ld, "coarse images"));
     RC(dalloc(c, &c->st, (size_t)kSingle * ld, "single states"));
     HC(hipMalloc((void**)&c->ism, 16 * sizeof(int)));
     HC(hipHostMalloc((void**)&c->h_ism, 16 * sizeof(int), hipHostMallocDefault));
@@ -359,7 +360,7 @@ int prh::autotune(pr_ctx* c, int ns) {
   RC(ensure_arena(c, ns, 1));
   if (ns > c->P + 1) return PR_OK;
   static const int nts[] = {128, 192, 256};
-  static const int zcs[] = {16, 32, 64, 128};
+  static const int zcs[] = {12, 20, 28, 32, 60, 64, 124, 128, 252};
   hipEvent_t e0, e1;
   HC(hipEventCreate(&e0));
   HC(hipEventCreate(&e1));
@@ -370,7 +371,7 @@ int prh::autotune(pr_ctx* c, int ns) {
     if (c->o.tile_nt && nt != c->o.tile_nt) continue;
     for (int zc : zcs) {
       if (c->o.tile_zc && zc != c->o.tile_zc) continue;
-      if (zc > zmax && zc != 16) continue;
+      if (zc > zmax && zc != 12) continue;
       HC(fine_step_launch(c, c->Q, c->ld, c->Qt, c->ld, ns, nt, zc));
       HC(hipEventRecord(e0, c->stream));
       for (int r = 0; r < 3; ++r)
@@ -494,14 +495,19 @@ static int gemm_nn_chunked(pr_ctx* c, double* Y, const double* A, int K,
 // pivoted factorisation and the copy of its rank to pinned memory;
 // update_mid (after that copy landed) the second pass; update_end the
 // append.
-int prh::update_begin(pr_ctx* c, const double* X0, const double* FX0, int b) {
+int prh::update_begin(pr_ctx* c, const double* X0, const double* FX0,
+                      const double* GX0, int b) {
   c->upd_b = b;
   if (b <= 0) return PR_OK;
   hipStream_t s = c->stream;
   const int64_t ld = c->ld, d = c->d;
   HC(hipMemcpyAsync(c->X, X0, (size_t)b * ld * 8, hipMemcpyDeviceToDevice, s));
-  RC(run_coarse(c, c->X, c->DX, b, ld, c->Yb, c->Wk, c->Rb));
-  HC(launch_sub(c->DX, FX0, c->DX, (int64_t)b * ld, s));
+  if (GX0) {
+    HC(launch_sub(c->DX, FX0, GX0, (int64_t)b * ld, s));
+  } else {
+    RC(run_coarse(c, c->X, c->DX, b, ld, c->Yb, c->Wk, c->Rb));
+    HC(launch_sub(c->DX, FX0, c->DX, (int64_t)b * ld, s));
+  }
   HC(launch_colnorm2(c->X, ld, b, d, c->part, c->n0, s));
   if (c->r > 0) {
     for (int pass = 0; pass < 2; ++pass) {
@@ -559,7 +565,7 @@ int prh::update_end(pr_ctx* c) {
 int prh::krylov_append(pr_ctx* c, const double* X0, const double* FX0, int b) {
   if (b <= 0) return PR_OK;
   RC(ensure_arena(c, b, c->r + b));
-  RC(update_begin(c, X0, FX0, b));
+  RC(update_begin(c, X0, FX0, nullptr, b));
   HC(hipStreamSynchronize(c->stream));
   RC(update_mid(c));
   HC(hipStreamSynchronize(c->stream));
@@ -610,6 +616,9 @@ int prh::coarse_init(pr_ctx* c) {
   for (int i = 0; i < c->P; ++i)
     RC(run_coarse(c, c->Q + (int64_t)i * c->ld, c->Q + (int64_t)(i + 1) * c->ld,
                   1, c->ld, single(c, kTa), single(c, kTb), single(c, kRs)));
+  // G(q^0_i) = q^0_{i+1}: the coarse images of the first iterates.
+  HC(hipMemcpyAsync(c->GQ, c->Q + c->ld, (size_t)c->P * c->ld * 8,
+                    hipMemcpyDeviceToDevice, c->stream));
   return PR_OK;
 }
 
@@ -625,15 +634,25 @@ int prh::chain(pr_ctx* c, int k) {
                     c->Qt + (int64_t)(k + 1) * ld, nullptr, nullptr, ld, 0,
                     nullptr, d, s));
   const int nblk = gemv_t_blocks(d);
+  double* y = single(c, kY);
   for (int i = k + 1; i < P; ++i) {
-    RC(run_coarse(c, da, g, 1, ld, single(c, kTa), single(c, kTb), single(c, kRs)));
+    // K(delta) = G(delta) + D(S) (S^T delta): the fine part (two passes over
+    // the basis) runs on the side stream while the coarse step runs here;
+    // both join before the combine.
     if (c->r > 0) {
-      HC(launch_gemv_t(c->S, ld, c->r, da, d, c->part, nblk, s));
-      HC(launch_reduce_cols(c->part, nblk, c->r, c->cvec, s));
+      HC(hipEventRecord(c->ev_fork, s));
+      HC(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+      HC(launch_gemv_t(c->S, ld, c->r, da, d, c->part, nblk, c->side));
+      HC(launch_reduce_cols(c->part, nblk, c->r, c->cvec, c->side));
+      HC(launch_lincomb(y, nullptr, c->D, ld, c->r, c->cvec, d, c->side));
+      HC(hipEventRecord(c->ev_join, c->side));
     }
-    HC(launch_combine(c->Q + (int64_t)(i + 1) * ld, i + 1 < P ? db : nullptr,
-                      c->Qt + (int64_t)(i + 1) * ld, g, c->D, ld, c->r,
-                      c->cvec, d, s));
+    RC(run_coarse(c, da, g, 1, ld, single(c, kTa), single(c, kTb), single(c, kRs)));
+    if (c->r > 0) HC(hipStreamWaitEvent(s, c->ev_join, 0));
+    // G(q^{k+1}_i) = G(q^k_i) + G(delta_i) by linearity.
+    HC(launch_combine3(c->Q + (int64_t)(i + 1) * ld, i + 1 < P ? db : nullptr,
+                       c->Qt + (int64_t)(i + 1) * ld, g, c->r > 0 ? y : nullptr,
+                       c->GQ + (int64_t)i * ld, d, s));
     std::swap(da, db);
   }
   return PR_OK;
@@ -709,7 +728,15 @@ static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
       RC(sweep());
     pts += (int64_t)ns * c->n * c->n_f;
     HC(hipEventRecord(ev[2 + 3 * k], s));
-    if (krylov) RC(krylov_append(c, c->Q + (int64_t)k * ld, c->Qt + (int64_t)(k + 1) * ld, P - k));
+    if (krylov) {
+      RC(ensure_arena(c, P - k, c->r + P - k));
+      RC(update_begin(c, c->Q + (int64_t)k * ld, c->Qt + (int64_t)(k + 1) * ld,
+                      c->GQ + (int64_t)k * ld, P - k));
+      HC(hipStreamSynchronize(s));
+      RC(update_mid(c));
+      HC(hipStreamSynchronize(s));
+      RC(update_end(c));
+    }
     HC(hipEventRecord(ev[3 + 3 * k], s));
     const int rr = c->r;
     RC(with_graph(c, gkey(3, k, rr), [&] { return chain(c, k); }));
@@ -808,10 +835,13 @@ extern "C" int pr_create_ex(const pr_grid* g, double c_s, double U,
       c->own_stream = true;
     }
   }
+  if (e == hipSuccess) e = hipStreamCreate(&c->side);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     set_error(nullptr, PR_EDEVICE, "HIP device/stream: %s", hipGetErrorString(e));
-    delete c;
+    pr_destroy(c);
     return PR_EDEVICE;
   }
   *out = c;
@@ -827,12 +857,18 @@ extern "C" void pr_destroy(pr_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   clear_graphs(c);
-  double* bufs[] = {c->Q, c->Qt, c->Wk, c->X, c->DX, c->Yb, c->Rb, c->st,
+  double* bufs[] = {c->Q, c->Qt, c->GQ, c->Wk, c->X, c->DX, c->Yb, c->Rb, c->st,
                     c->S, c->D, c->small, c->ext_ping, c->ext_io};
   for (double* p : bufs)
     if (p) (void)hipFree(p);
   if (c->ism) (void)hipFree(c->ism);
   if (c->h_ism) (void)hipHostFree(c->h_ism);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

@@ -45,7 +45,7 @@ def test_fine_forms_and_tiles_agree(nx, nz, U):
     ref = binding.Context.from_problem(prob, tile_nt=256,
                                        tile_zc=64).fine_sweep(Q)
     for nt in (128, 192, 256):
-        for zc in (8, 16, 32, 64, 128):
+        for zc in (8, 12, 28, 32, 60, 124):
             say(f"  tile {nt}x{zc}")
             got = binding.Context.from_problem(prob, tile_nt=nt,
                                                tile_zc=zc).fine_sweep(Q)

@@ -111,7 +111,7 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(dt_g=0.0), "time steps"),
     (dict(n_sound=0), "n_sound"),
     (dict(tile_nt=100), "tile_nt"),
-    (dict(tile_zc=12), "tile_zc"),
+    (dict(tile_zc=10), "tile_zc"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
     args = dict(nx=64, nz=32, c_s=1.0, U=0.1, dt_f=0.2 / 64, dt_g=2.0 / 64,
