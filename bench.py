@@ -30,6 +30,32 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_POINT_STEP = 48.0   # read and write u, w, p once per RK-3 step
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fine_step_traffic_c2_512x256.md")
+FINE_SRC = os.path.join(ROOT, "paper_1510_02237_amd", "csrc", "fine.hip")
+
+
+def fine_src_hash():
+    import hashlib
+    return hashlib.sha256(open(FINE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per grid-point step of k_fine_step from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary, if it was taken on the current
+    kernel source; else None."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if line.startswith("traffic_bytes_per_point_step:"):
+            vals["b"] = float(line.split(":", 1)[1])
+        if line.startswith("fine_hip_sha256_16:"):
+            vals["h"] = line.split(":", 1)[1].strip()
+    if vals.get("h") != fine_src_hash() or "b" not in vals:
+        return None
+    return vals["b"]
 
 
 def _rel_l2(a, b):
@@ -148,6 +174,12 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed batched solves (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the served stream (--serve requests at "
+                         "--serve-rate) and print its summary")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="end with one device-to-device copy of this many "
+                         "MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -158,6 +190,14 @@ def main():
     import numpy as np
     import torch
     from paper_1510_02237_amd import binding, workloads as W
+
+    if args.serve_only:
+        out = serve_leg(args.serve, args.serve_rate, timeout=1e9)
+        out["config"] = dict(workload="served stream", grids=list(W.SERVE_GRIDS),
+                             slices=list(W.SERVE_SLICES), K=4, U="U[0, 0.3]",
+                             max_inflight=8)
+        print(json.dumps(out))
+        return
 
     prob, K, u0 = W.config(args.workload)
     dev = torch.device("cuda:0")
@@ -170,6 +210,8 @@ def main():
     n_fine_launches = args.steps * K * ctx_nf(prob)
     kernel_ms = ms_fine / n_fine_launches
     achieved = BYTES_PER_POINT_STEP * pts / (ms_fine * 1e-3) / 1e9
+    tb = measured_traffic()
+    traffic = None if tb is None else tb * pts / n_fine_launches
     res = dict(
         metric="Parareal wall-time vs serial fine on GPU; stencil GB/s; "
                "p50/p99 served latency",
@@ -185,9 +227,12 @@ def main():
                        total=st["ms_total"]),
         ranks=st["rank"],
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS,
-                      unit="GB/s", frac=achieved / HBM_PEAK_GBPS, traffic=None,
-                      kernel="k_fine_step", kernel_avg_ms=kernel_ms,
-                      bytes_per_point_step=BYTES_PER_POINT_STEP),
+                      unit="GB/s", frac=achieved / HBM_PEAK_GBPS,
+                      traffic=traffic, kernel="k_fine_step",
+                      kernel_avg_ms=kernel_ms,
+                      bytes_per_point_step=BYTES_PER_POINT_STEP,
+                      algorithmic_bytes_per_launch=BYTES_PER_POINT_STEP * pts / n_fine_launches,
+                      fine_hip_sha256_16=fine_src_hash()),
         fine_point_updates_per_s=pts / (ms_fine * 1e-3),
     )
     if not args.no_extras:
@@ -216,6 +261,14 @@ def main():
         res["cpu_baseline"] = cpu_baseline(prob, u0, K)
         res["cpu_baseline"]["cpu_model"] = cpu_model()
         res["cpu_baseline"]["nproc"] = os.cpu_count()
+    if args.calibrate_copy_mb > 0:
+        n = args.calibrate_copy_mb * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        res["calibration_copy_bytes"] = n * 8
     print(json.dumps(res))
 
 

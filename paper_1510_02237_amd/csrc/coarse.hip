@@ -30,15 +30,17 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-constexpr int TX = 32, TZ = 32, NT = 1024;
 constexpr int HXM = 2 * kCoarseMaxSubPerLaunch + 1;
 constexpr int HZM = 2 * kCoarseMaxSubPerLaunch;
-constexpr int RXM = TX + 2 * HXM, RZM = TZ + 2 * HZM;
-constexpr int SX = RXM + 2;                         // padded LDS row stride
-constexpr int LDSN = (RZM + 2) * SX;
-constexpr int MPT = (RXM * RZM + NT - 1) / NT;      // points per thread
 
+// TX x TZ interior tile, NT threads.  A single state uses the shorter tile
+// (twice the workgroups for a latency-bound launch); batches use 32 x 32.
+template <int TX, int TZ, int NT>
 __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
+  constexpr int RXM = TX + 2 * HXM, RZM = TZ + 2 * HZM;
+  constexpr int SX = RXM + 2;                     // padded LDS row stride
+  constexpr int LDSN = (RZM + 2) * SX;
+  constexpr int MPT = (RXM * RZM + NT - 1) / NT;  // points per thread
   __shared__ double su[LDSN], sw[LDSN], sp[LDSN];
   const int nx = L.nx, nz = L.nz;
   const int64_t n = (int64_t)nx * nz;
@@ -185,8 +187,15 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
 hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s) {
   if (L.nsub < 1 || L.nsub > kCoarseMaxSubPerLaunch || L.nstates < 1)
     return hipErrorInvalidValue;
-  const int tiles = ((L.nx + TX - 1) / TX) * ((L.nz + TZ - 1) / TZ);
-  hipLaunchKernelGGL(k_coarse, dim3(tiles, L.nstates), dim3(NT), 0, s, L);
+  const int big = ((L.nx + 31) / 32) * ((L.nz + 31) / 32);
+  if ((int64_t)big * L.nstates < 256) {
+    const int tiles = ((L.nx + 31) / 32) * ((L.nz + 15) / 16);
+    hipLaunchKernelGGL((k_coarse<32, 16, 1024>), dim3(tiles, L.nstates),
+                       dim3(1024), 0, s, L);
+  } else {
+    hipLaunchKernelGGL((k_coarse<32, 32, 1024>), dim3(big, L.nstates),
+                       dim3(1024), 0, s, L);
+  }
   return hipGetLastError();
 }
 

@@ -101,7 +101,7 @@ struct Pooled {
 };
 
 constexpr size_t kQueueCap = 4096;
-constexpr int kServerNT = 256, kServerZC = 32;
+constexpr int kServerNT = 192, kServerZC = 28;
 
 }  // namespace
 

@@ -1,0 +1,98 @@
+"""Parity at the benchmark's full size (512 x 256 grid, P = 32, K = 4) in
+the launch configuration bench.py times (batched form, autotuned tile).
+
+The oracle cannot run the whole solve here in seconds, so: sampled slices
+of a full 32-slice fine sweep and a coarse step are compared with the oracle
+one by one; the whole solve is checked against the oracle's own run of the
+same workload stored in tests/golden (error of every iterate against the
+serial fine run, ranks, sampled values of the final iterate) and through
+properties that hold at any size (Section 2.1 and 2.2): the basis rank
+sequence sum_j (P - j), the bitwise agreement of the batched and plain
+forms, the exactness of K = P iterations (bitwise the serial fine run) and
+homogeneity.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.operators import Params
+from paper_1510_02237_amd import binding, workloads as W
+from gpu_cases import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2():
+    prob, K, u0 = W.config("c2_512x256")
+    return prob, K, u0
+
+
+def test_full_batch_fine_sweep_sampled(c2):
+    torch = pytest.importorskip("torch")
+    prob, K, u0 = c2
+    P = prob["P"]
+    rng = np.random.default_rng(12)
+    Q = rng.normal(size=(P, 3, prob["nz"], prob["nx"]))
+    say("full-size sweep 512x256 x 32")
+    ctx = binding.Context.from_problem(prob)
+    FQ = ctx.fine_sweep(torch.from_numpy(Q).cuda()).cpu().numpy()
+    prm = Params(**prob)
+    for s in (0, 17, P - 1):
+        assert rel_l2(FQ[s], oracle.fine_F(Q[s], prm)) <= 1e-12, s
+
+
+def test_full_size_coarse_step(c2):
+    prob, K, u0 = c2
+    say("full-size coarse")
+    ctx = binding.Context.from_problem(prob)
+    want = oracle.coarse_G(u0, Params(**prob))
+    assert rel_l2(ctx.coarse_step(u0), want) <= 1e-12
+
+
+FIXTURE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "c2_512x256_oracle.json")
+
+
+def test_full_size_solve_properties(c2):
+    torch = pytest.importorskip("torch")
+    prob, K, u0 = c2
+    P = prob["P"]
+    say("full-size solve")
+    u0d = torch.from_numpy(u0).cuda()
+    ctx = binding.Context.from_problem(prob)
+    a = ctx.solve(u0d, K).cpu().numpy()
+    assert ctx.stats()["rank"] == [32, 63, 93, 122]
+    plain = binding.Context.from_problem(prob, form="plain")
+    assert np.array_equal(plain.solve(u0d, K).cpu().numpy(), a)
+    assert np.array_equal(ctx.solve(2.0 * u0d, K).cpu().numpy(), 2.0 * a)
+    say("full-size K = P")
+    ref = ctx.serial_fine(u0d).cpu().numpy()
+    assert np.array_equal(ctx.solve(u0d, P).cpu().numpy(), ref)
+
+
+def test_full_size_solve_matches_oracle_fixture(c2):
+    """Against the oracle's own run of the same workload (fixture written by
+    tests/golden/make_c2_fixture.py): the error of every iterate against the
+    serial fine run (eq. errorDef), the basis ranks, and 64 sampled values
+    of the final iterate within 1e-10 of its largest entry."""
+    torch = pytest.importorskip("torch")
+    fx = json.load(open(FIXTURE))
+    prob, K, u0 = c2
+    say("full-size solve vs oracle fixture")
+    u0d = torch.from_numpy(u0).cuda()
+    ctx = binding.Context.from_problem(prob)
+    ref = ctx.serial_fine(u0d).cpu().numpy()
+    for k in range(K + 1):
+        got = ctx.solve(u0d, k).cpu().numpy()
+        assert abs(rel_l2(got, ref) - fx["eps_vs_serial_fine"][k]) <= 1e-9, k
+    assert ctx.stats()["rank"] == fx["ranks"]
+    flat = got.ravel()
+    idx = np.array(fx["sample_index"])
+    want = np.array(fx["sample_value"])
+    assert np.abs(flat[idx] - want).max() <= 1e-10 * fx["final_max"]
+    assert abs(np.linalg.norm(flat) - fx["final_norm2"]) <= 1e-10 * fx["final_norm2"]
