@@ -93,7 +93,10 @@ typedef struct pr_opts {
                              propagation of slices i < k, whose inputs are
                              bitwise those of iteration k-1 (Section 2.1:
                              after k iterations slices 0..k are exact)         */
-  int32_t tile_nt;        /* fine-sweep threads per workgroup, 0 = autotune    */
+  int32_t tile_nt;        /* fine-sweep threads per workgroup: 128, 192 or 256
+                             (tiles with an x-halo), or nx when nx is 128, 256
+                             or 512 (one workgroup per periodic row, no halo);
+                             0 = autotune                                      */
   int32_t tile_zc;        /* fine-sweep output rows per workgroup (multiple of
                              4), 0 = autotune                                  */
 } pr_opts;

@@ -14,6 +14,11 @@
 // x come from the LDS rings, neighbours along z from per-thread register
 // windows.  The halo is 3 columns on the upwind side and 2 on the other per
 // stage (15 per step) and 6 rows above and below the chunk.
+//
+// When one workgroup spans a whole periodic row (NT = nx, FULL) there is no
+// x-halo at all: the three columns beyond each end of an LDS row hold copies
+// of the columns at the other end, written with the row, so every thread
+// computes an output column.
 #include "pr_internal.h"
 
 namespace prh {
@@ -60,51 +65,58 @@ struct Carry {
   double du0, dw0;            // D_u, D_w at row r
 };
 
-// Reads u, w at offsets +-1 of the next row (rn) and returns its D_u, D_w.
-template <int W>
-__device__ __forceinline__ void carry_read(const double (*rn)[W], int c,
-                                           double& um, double& up,
-                                           double& wm, double& wp) {
-  um = rn[0][c - 1];
-  up = rn[0][c + 1];
-  wm = rn[1][c - 1];
-  wp = rn[1][c + 1];
+// LDS ring layout: column-major, one LDS column of CS doubles per x
+// position holding the 3 levels x 4 row slots x 3 fields of that position
+// (CS odd, so 16 consecutive lanes reading 8-byte words hit distinct bank
+// pairs).  A thread addresses everything from one base, its own column, with
+// small constant offsets: value (level, slot, field) of column c + dx is at
+// base + dx * CS + (level * 4 + slot) * 3 + field.
+constexpr int CS = 37;
+
+// Reads u, w at offsets +-1 of the next row (rn: own column of that row).
+__device__ __forceinline__ void carry_read(const double* rn, double& um,
+                                           double& up, double& wm,
+                                           double& wp) {
+  um = rn[-CS];
+  up = rn[CS];
+  wm = rn[1 - CS];
+  wp = rn[1 + CS];
 }
 
-// Right-hand side at one point of row r.  rc: LDS row r of the level
-// ([3][W], fields u, w, p); c: this thread's column in the padded row;
+// Right-hand side at one point of row r.  rc: this thread's column of LDS
+// row r of the level (fields u, w, p at rc[0], rc[1], rc[2]);
 // the own-column values along z come from registers, the +-1 neighbours
 // of u and w and the D differences from the carry, D_u, D_w of row r + 1
 // from the caller.
-template <int SGN, int W>
+template <int SGN>
 __device__ __forceinline__ void rhs_point(
-    const double (*rc)[W], int c, const Carry& cy, double dup, double dwp,
+    const double* rc, const Carry& cy, double dup, double dwp,
     double u0, double wm2, double wm1, double w0, double wp1, double wp2,
     double pm2, double pm1, double p0, double pp1, double pp2, const Coef& k,
     double& fu, double& fw, double& fp) {
-  const double* U = rc[0];
-  const double* Wr = rc[1];
-  const double* Pr = rc[2];
+  // field f at x-offset dx
+  auto U = [&](int dx) { return rc[dx * CS]; };
+  auto Wr = [&](int dx) { return rc[dx * CS + 1]; };
+  auto Pr = [&](int dx) { return rc[dx * CS + 2]; };
   const double um1 = cy.xum, up1 = cy.xup, wxm1 = cy.xwm, wxp1 = cy.xwp;
-  const double um2 = U[c - 2], up2 = U[c + 2];
-  const double wxm2 = Wr[c - 2], wxp2 = Wr[c + 2];
-  const double pxm2 = Pr[c - 2], pxm1 = Pr[c - 1], pxp1 = Pr[c + 1],
-               pxp2 = Pr[c + 2];
+  const double um2 = U(-2), up2 = U(2);
+  const double wxm2 = Wr(-2), wxp2 = Wr(2);
+  const double pxm2 = Pr(-2), pxm1 = Pr(-1), pxp1 = Pr(1), pxp2 = Pr(2);
   double au, aw, ap;
   if (SGN > 0) {  // offsets -3 .. +2
-    au = k.a0 * U[c - 3] + k.a1 * um2 + k.a2 * um1 + k.a3 * u0 + k.a4 * up1 +
+    au = k.a0 * U(-3) + k.a1 * um2 + k.a2 * um1 + k.a3 * u0 + k.a4 * up1 +
          k.a5 * up2;
-    aw = k.a0 * Wr[c - 3] + k.a1 * wxm2 + k.a2 * wxm1 + k.a3 * w0 +
+    aw = k.a0 * Wr(-3) + k.a1 * wxm2 + k.a2 * wxm1 + k.a3 * w0 +
          k.a4 * wxp1 + k.a5 * wxp2;
-    ap = k.a0 * Pr[c - 3] + k.a1 * pxm2 + k.a2 * pxm1 + k.a3 * p0 +
+    ap = k.a0 * Pr(-3) + k.a1 * pxm2 + k.a2 * pxm1 + k.a3 * p0 +
          k.a4 * pxp1 + k.a5 * pxp2;
   } else {  // offsets -2 .. +3
     au = k.a0 * um2 + k.a1 * um1 + k.a2 * u0 + k.a3 * up1 + k.a4 * up2 +
-         k.a5 * U[c + 3];
+         k.a5 * U(3);
     aw = k.a0 * wxm2 + k.a1 * wxm1 + k.a2 * w0 + k.a3 * wxp1 + k.a4 * wxp2 +
-         k.a5 * Wr[c + 3];
+         k.a5 * Wr(3);
     ap = k.a0 * pxm2 + k.a1 * pxm1 + k.a2 * p0 + k.a3 * pxp1 + k.a4 * pxp2 +
-         k.a5 * Pr[c + 3];
+         k.a5 * Pr(3);
   }
   const double dx4p = (pxm2 - pxp2) + 8.0 * (pxp1 - pxm1);
   const double dz4p = (pm2 - pp2) + 8.0 * (pp1 - pm1);
@@ -117,15 +129,16 @@ __device__ __forceinline__ void rhs_point(
   fp = ap - k.cx4 * dx4u - k.cz4 * dz4w;
 }
 
-template <int SGN, int NT, int PF>
-__global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
+template <int SGN, int NT, int PF, bool FULL>
+__global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
+    const FineLaunch L) {
   constexpr int HL = SGN > 0 ? 3 : 2;  // reach on the upwind side
   constexpr int HR = 5 - HL;
-  constexpr int TX = NT - 15;
+  constexpr int TX = FULL ? NT : NT - 15;
   constexpr int PAD = 3;
   constexpr int W = NT + 2 * PAD;
   static_assert(8 % PF == 0, "prefetch depth must divide the unroll");
-  __shared__ double ring[3][4][3][W];  // level, row slot, field, column
+  __shared__ double ring[W * CS];  // column-major, see CS
 
   const int lb = xcd_logical_block(L.nblocks);
   if (lb >= L.nblocks) return;
@@ -152,18 +165,22 @@ __global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
   const int zc = L.zc;
   const int x0 = xt * TX;
   const int z0 = zt * zc;
-  const int gx = wrap(x0 - 3 * HL + t, nx);
-  const int xo = x0 + t - 3 * HL;
-  const bool store_col = (t >= 3 * HL) && (t < NT - 3 * HR) && (xo < nx);
+  const int gx = FULL ? t : wrap(x0 - 3 * HL + t, nx);
+  const int xo = FULL ? t : x0 + t - 3 * HL;
+  const bool store_col =
+      FULL || ((t >= 3 * HL) && (t < NT - 3 * HR) && (xo < nx));
+  // FULL: the lanes whose column is copied into a pad of the row
+  const bool pad_lo = FULL && t < PAD, pad_hi = FULL && t >= NT - PAD;
   const int nrows = zc + 12;
 
   // Pads of every ring row are read by the edge columns (whose results are
-  // discarded); keep them finite.
-  for (int q = t; q < 3 * 4 * 3 * 2 * PAD; q += NT) {
-    const int row = q / (2 * PAD), e = q % (2 * PAD);
-    double* r = &ring[0][0][0][0] + row * W;
-    r[e < PAD ? e : NT + e] = 0.0;
+  // discarded, or, for FULL, overwritten with copies); keep them finite.
+  for (int q = t; q < 2 * PAD * CS; q += NT) {
+    const int col = q / CS, e = q % CS;
+    ring[(col < PAD ? col : NT + col) * CS + e] = 0.0;
   }
+  double* const own = ring + c * CS;  // this thread's LDS column
+  auto slot = [&](int lvl, int sl) { return own + (lvl * 4 + sl) * 3; };
 
   double fu_[PF], fw_[PF], fp_[PF];  // prefetched input rows
 #pragma unroll
@@ -179,6 +196,20 @@ __global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
   double bu[8], bw[8], bp[8];  // stage-2 rows
   Carry c1{}, c2{}, c3{};      // per-stage carries
 
+  // Writes this thread's column of one ring row (and, for FULL, its copy in
+  // the pad at the other end of the row).
+  auto ring_put = [&](double* r, double vu, double vw, double vp) {
+    r[0] = vu;
+    r[1] = vw;
+    r[2] = vp;
+    if (FULL && (pad_lo || pad_hi)) {
+      double* rr = r + (pad_lo ? NT : -NT) * CS;
+      rr[0] = vu;
+      rr[1] = vw;
+      rr[2] = vp;
+    }
+  };
+
   // One row iteration.  For each stage L, PREL reads the +-1 neighbours of
   // the row after the one it computes (from an earlier iteration) and
   // advances the carry; DOL computes the row.  All flags are compile-time
@@ -189,11 +220,11 @@ __global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
 #define PR_STAGE(PRE, DO, LVL, CY, ZU, ZW, ZP, BU, BW, BP, OU, OW, OP, BETA, STORE) \
   if (PRE) {                                                                  \
     double xum, xup, xwm, xwp;                                                \
-    carry_read<W>(ring[LVL][((uu) - 1) & 3], c, xum, xup, xwm, xwp);          \
+    carry_read(slot(LVL, ((uu) - 1) & 3), xum, xup, xwm, xwp);                \
     const double dup = xup - xum, dwp = xwp - xwm;                            \
     if (DO) {                                                                 \
       double fu, fw, fp;                                                      \
-      rhs_point<SGN, W>(ring[LVL][((uu) - 2) & 3], c, CY, dup, dwp,           \
+      rhs_point<SGN>(slot(LVL, ((uu) - 2) & 3), CY, dup, dwp,                 \
                         ZU[((uu) - 2) & 7], ZW[((uu) - 4) & 7],               \
                         ZW[((uu) - 3) & 7], ZW[((uu) - 2) & 7],               \
                         ZW[((uu) - 1) & 7], ZW[(uu) & 7], ZP[((uu) - 4) & 7], \
@@ -221,9 +252,7 @@ __global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
       iu[uu] = fu_[q];                                                        \
       iw[uu] = fw_[q];                                                        \
       ip[uu] = fp_[q];                                                        \
-      ring[0][(uu) & 3][0][c] = iu[uu];                                       \
-      ring[0][(uu) & 3][1][c] = iw[uu];                                       \
-      ring[0][(uu) & 3][2][c] = ip[uu];                                       \
+      ring_put(slot(0, (uu) & 3), iu[uu], iw[uu], ip[uu]);                    \
       const double* src = in + (int64_t)wrap(z0 - 6 + (it) + PF, nz) * nx + gx; \
       fu_[q] = src[0];                                                        \
       fw_[q] = src[n];                                                        \
@@ -232,13 +261,11 @@ __global__ __launch_bounds__(NT, 2) void k_fine_step(const FineLaunch L) {
     PR_STAGE(P1, D1, 0, c1, iu, iw, ip, iu[((uu) - 2) & 7],                   \
              iw[((uu) - 2) & 7], ip[((uu) - 2) & 7], au, aw, ap, b1,          \
              au[uu] = nu; aw[uu] = nw; ap[uu] = np;                           \
-             ring[1][(uu) & 3][0][c] = nu; ring[1][(uu) & 3][1][c] = nw;      \
-             ring[1][(uu) & 3][2][c] = np;)                                   \
+             ring_put(slot(1, (uu) & 3), nu, nw, np);)                        \
     PR_STAGE(P2, D2, 1, c2, au, aw, ap, iu[((uu) - 4) & 7],                   \
              iw[((uu) - 4) & 7], ip[((uu) - 4) & 7], bu, bw, bp, b2,          \
              bu[uu] = nu; bw[uu] = nw; bp[uu] = np;                           \
-             ring[2][(uu) & 3][0][c] = nu; ring[2][(uu) & 3][1][c] = nw;      \
-             ring[2][(uu) & 3][2][c] = np;)                                   \
+             ring_put(slot(2, (uu) & 3), nu, nw, np);)                        \
     PR_STAGE(P3, D3, 2, c3, bu, bw, bp, iu[((uu) - 6) & 7],                   \
              iw[((uu) - 6) & 7], ip[((uu) - 6) & 7], bu, bw, bp, dt,          \
              const int z3 = z0 + (it) - 12;                                   \
@@ -321,34 +348,85 @@ __global__ __launch_bounds__(256) void k_fine_stage(
   O[2 * n + idx] = B[2 * n + idx] + beta * fp;
 }
 
-template <int SGN, int NT>
+template <int SGN, int NT, bool FULL>
 hipError_t launch_nt(const FineLaunch& L, hipStream_t s) {
   const int grid = 8 * ((L.nblocks + 7) / 8);
-  hipLaunchKernelGGL((k_fine_step<SGN, NT, 4>), dim3(grid), dim3(NT), 0, s,
-                     L);
+  hipLaunchKernelGGL((k_fine_step<SGN, NT, 4, FULL>), dim3(grid), dim3(NT), 0,
+                     s, L);
   return hipGetLastError();
 }
 
 template <int SGN>
-hipError_t launch_sgn(const FineLaunch& L, int nt, hipStream_t s) {
+hipError_t launch_sgn(const FineLaunch& L, int nt, bool full, hipStream_t s) {
+  if (full) {
+    switch (nt) {
+      case 128: return launch_nt<SGN, 128, true>(L, s);
+      case 256: return launch_nt<SGN, 256, true>(L, s);
+      case 512: return launch_nt<SGN, 512, true>(L, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (nt) {
-    case 128: return launch_nt<SGN, 128>(L, s);
-    case 192: return launch_nt<SGN, 192>(L, s);
-    case 256: return launch_nt<SGN, 256>(L, s);
+    case 128: return launch_nt<SGN, 128, false>(L, s);
+    case 192: return launch_nt<SGN, 192, false>(L, s);
+    case 256: return launch_nt<SGN, 256, false>(L, s);
     default: return hipErrorInvalidValue;
+  }
+}
+
+template <int SGN, int NT, bool FULL>
+int blocks_per_cu() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&k_fine_step<SGN, NT, 4, FULL>),
+          NT, 0) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+template <int SGN>
+int blocks_per_cu_sgn(int nt, bool full) {
+  if (full) {
+    switch (nt) {
+      case 128: return blocks_per_cu<SGN, 128, true>();
+      case 256: return blocks_per_cu<SGN, 256, true>();
+      case 512: return blocks_per_cu<SGN, 512, true>();
+      default: return 0;
+    }
+  }
+  switch (nt) {
+    case 128: return blocks_per_cu<SGN, 128, false>();
+    case 192: return blocks_per_cu<SGN, 192, false>();
+    case 256: return blocks_per_cu<SGN, 256, false>();
+    default: return 0;
   }
 }
 
 }  // namespace
 
-bool fine_nt_supported(int nt) {
+bool fine_nt_supported(int nt, int nx) {
+  if (nt == nx) return fine_full_row(nx);
   return nt == 128 || nt == 192 || nt == 256;
+}
+
+bool fine_full_row(int nx) { return nx == 128 || nx == 256 || nx == 512; }
+
+int fine_blocks_per_cu(int nt, int nx, int sgn) {
+  const bool full = nt == nx && fine_full_row(nx);
+  return sgn >= 0 ? blocks_per_cu_sgn<1>(nt, full)
+                  : blocks_per_cu_sgn<-1>(nt, full);
 }
 
 hipError_t launch_fine_step(const FineLaunch& L, int nt, int sgn,
                             hipStream_t s) {
   if (L.nblocks <= 0) return hipSuccess;
-  return sgn >= 0 ? launch_sgn<1>(L, nt, s) : launch_sgn<-1>(L, nt, s);
+  // One tile width for every job of the launch; FULL when it is the row.
+  const bool full = nt == L.job[0].nx && fine_full_row(nt);
+  for (int j = 1; j < L.njobs; ++j)
+    if ((L.job[j].nx == nt && fine_full_row(nt)) != full)
+      return hipErrorInvalidValue;
+  return sgn >= 0 ? launch_sgn<1>(L, nt, full, s)
+                  : launch_sgn<-1>(L, nt, full, s);
 }
 
 hipError_t launch_fine_stage(const double* in, int64_t in_stride,

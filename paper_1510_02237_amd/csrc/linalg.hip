@@ -135,7 +135,7 @@ __global__ __launch_bounds__(256) void k_reduce_cols(
 }
 
 constexpr int COMB_NT = 256;
-constexpr int COMB_E = 4;
+constexpr int COMB_E = 2;
 constexpr int COMB_MAXC = 4096;
 
 // nw = qt + (g + sum_j D[j] c[j]); delta = nw - q; q = nw.   (mode 0)
@@ -154,6 +154,22 @@ __global__ __launch_bounds__(COMB_NT) void k_combine(
 #pragma unroll
   for (int e = 0; e < COMB_E; ++e) acc[e] = 0.0;
   int j = 0;
+  for (; j + 8 <= ncols; j += 8) {
+    const double* d0 = D + (int64_t)j * ld;
+#pragma unroll
+    for (int e = 0; e < COMB_E; ++e) {
+      const int64_t i = x0 + e * COMB_NT;
+      if (i < d) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = d0[(int64_t)q * ld + i];
+        acc[e] += ((v[0] * cs[j] + v[1] * cs[j + 1]) +
+                   (v[2] * cs[j + 2] + v[3] * cs[j + 3])) +
+                  ((v[4] * cs[j + 4] + v[5] * cs[j + 5]) +
+                   (v[6] * cs[j + 6] + v[7] * cs[j + 7]));
+      }
+    }
+  }
   for (; j + 4 <= ncols; j += 4) {
     const double c0 = cs[j], c1 = cs[j + 1], c2 = cs[j + 2], c3 = cs[j + 3];
     const double* d0 = D + (int64_t)j * ld;
@@ -538,23 +554,33 @@ __global__ __launch_bounds__(PC_NT) void k_pchol(
   if (t == 0) *rank_out = rho;
 }
 
-// Same factorisation for b <= 128 by one wavefront with the factor L in
-// LDS: the pivot search is a wave reduction, and no workgroup barrier is
-// needed inside the factorisation.
-constexpr int PC1_MAX = 128;
-
+// Same factorisation for b <= BMAX by one wavefront with the factor L, the
+// Gram matrix (when it fits) and R^{-1} in LDS: the pivot search is a wave
+// reduction, and no workgroup barrier is needed inside the factorisation.
+// L is stored by columns (Lc[i][j] = L[j][i]) and the Gram read by rows, so
+// the lanes of a wave, one per position j, touch consecutive LDS words.
+// R^{-1} is formed by back substitution one row at a time, lane c owning
+// column c: row i of R^{-1} needs rows i+1.. of its own column only.
+template <int BMAX, bool GLDS>
 __global__ __launch_bounds__(64) void k_pchol_wave(
     const double* __restrict__ G, int b, const double* __restrict__ n0,
     double* r11sq, double rank_tol2, double rel2, int pivot,
     double* __restrict__ T, int* rank_out) {
-  __shared__ double L[PC1_MAX * PC1_MAX];
-  __shared__ double diag[PC1_MAX];
-  __shared__ int perm[PC1_MAX];
+  __shared__ double Lc[BMAX * BMAX];
+  __shared__ double Gs[GLDS ? BMAX * BMAX : 1];
+  __shared__ double diag[BMAX];
+  __shared__ int perm[BMAX];
   const int t = threadIdx.x;
+  if (GLDS)
+    for (int q = t; q < b * b; q += 64) Gs[(q / b) * BMAX + q % b] = G[q];
   for (int q = t; q < b; q += 64) {
     diag[q] = G[(int64_t)q * b + q];
     perm[q] = q;
   }
+  // G is symmetric: entry (ck, j) is read along row ck.
+  auto grow = [&](int i, int j) {
+    return GLDS ? Gs[i * BMAX + j] : G[(int64_t)i * b + j];
+  };
   double m = 0.0;
   if (pivot && n0)
     for (int q = t; q < b; q += 64) m = fmax(m, n0[q]);
@@ -566,7 +592,6 @@ __global__ __launch_bounds__(64) void k_pchol_wave(
   if (t == 0 && r11sq && pivot) *r11sq = m;
   int rho = b;
   for (int k = 0; k < b; ++k) {
-    int p = k;
     if (pivot) {
       double best = -1.0;
       int bi = b;
@@ -578,14 +603,14 @@ __global__ __launch_bounds__(64) void k_pchol_wave(
         const int i2 = __shfl_xor(bi, o, 64);
         if (v2 > best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
       }
-      p = bi;
+      const int p = bi;
       const double thr = fmax(abs2, rel2 * n0[perm[p]]);
       if (!(best > thr)) { rho = k; break; }
       if (p != k) {
         for (int i = t; i < k; i += 64) {
-          const double a = L[k * PC1_MAX + i];
-          L[k * PC1_MAX + i] = L[p * PC1_MAX + i];
-          L[p * PC1_MAX + i] = a;
+          const double a = Lc[i * BMAX + k];
+          Lc[i * BMAX + k] = Lc[i * BMAX + p];
+          Lc[i * BMAX + p] = a;
         }
         __syncthreads();
         if (t == 0) {
@@ -601,24 +626,42 @@ __global__ __launch_bounds__(64) void k_pchol_wave(
     const double lkk = sqrt(diag[k]);
     const int ck = perm[k];
     for (int jj = k + 1 + t; jj < b; jj += 64) {
-      double sacc = G[(int64_t)perm[jj] * b + ck];
-      for (int i = 0; i < k; ++i) sacc -= L[jj * PC1_MAX + i] * L[k * PC1_MAX + i];
+      double sacc = grow(ck, perm[jj]);
+      for (int i = 0; i < k; ++i) sacc -= Lc[i * BMAX + jj] * Lc[i * BMAX + k];
       const double l = sacc / lkk;
-      L[jj * PC1_MAX + k] = l;
+      Lc[k * BMAX + jj] = l;
       diag[jj] -= l * l;
     }
-    if (t == 0) L[k * PC1_MAX + k] = lkk;
+    if (t == 0) Lc[k * BMAX + k] = lkk;
     __syncthreads();
   }
-  for (int q = t; q < b * b; q += 64) T[q] = 0.0;
+  // X = R^{-1} (upper triangular, R[i][mm] = Lc[i][mm]).  With the Gram in
+  // LDS, X takes its place; T[perm[i]][c] = X[i][c] at the end.  Otherwise X
+  // is built in T directly through perm.
   __syncthreads();
-  for (int cc = t; cc < rho; cc += 64) {
-    T[(int64_t)perm[cc] * b + cc] = 1.0 / L[cc * PC1_MAX + cc];
-    for (int i = cc - 1; i >= 0; --i) {
-      double sacc = 0.0;
-      for (int mm = i + 1; mm <= cc; ++mm)
-        sacc += L[mm * PC1_MAX + i] * T[(int64_t)perm[mm] * b + cc];
-      T[(int64_t)perm[i] * b + cc] = -sacc / L[i * PC1_MAX + i];
+  auto xat = [&](int i, int c) -> double& {
+    return GLDS ? Gs[i * BMAX + c] : T[(int64_t)perm[i] * b + c];
+  };
+  if (!GLDS) {
+    for (int q = t; q < b * b; q += 64) T[q] = 0.0;
+    __syncthreads();
+  }
+  for (int c = t; c < rho; c += 64) {
+    for (int i = rho - 1; i >= 0; --i) {
+      if (i > c) {
+        if (GLDS) xat(i, c) = 0.0;
+        continue;
+      }
+      double sacc = i == c ? 1.0 : 0.0;
+      for (int mm = i + 1; mm <= c; ++mm) sacc -= Lc[i * BMAX + mm] * xat(mm, c);
+      xat(i, c) = sacc / Lc[i * BMAX + i];
+    }
+  }
+  __syncthreads();
+  if (GLDS) {
+    for (int q = t; q < b * b; q += 64) {
+      const int i = q / b, c = q % b;  // position i, column c
+      T[(int64_t)perm[i] * b + c] = (i < rho && c < rho) ? Gs[i * BMAX + c] : 0.0;
     }
   }
   if (t == 0) *rank_out = rho;
@@ -802,9 +845,12 @@ hipError_t launch_pchol(const double* G, int b, const double* n0,
                         double* r11sq, double rank_tol2, double rel2,
                         int pivot, double* T, int* rank, double* work,
                         hipStream_t s) {
-  if (b <= PC1_MAX)
-    hipLaunchKernelGGL(k_pchol_wave, dim3(1), dim3(64), 0, s, G, b, n0, r11sq,
-                       rank_tol2, rel2, pivot, T, rank);
+  if (b <= 64)
+    hipLaunchKernelGGL((k_pchol_wave<64, true>), dim3(1), dim3(64), 0, s, G, b,
+                       n0, r11sq, rank_tol2, rel2, pivot, T, rank);
+  else if (b <= 128)
+    hipLaunchKernelGGL((k_pchol_wave<128, false>), dim3(1), dim3(64), 0, s, G,
+                       b, n0, r11sq, rank_tol2, rel2, pivot, T, rank);
   else
     hipLaunchKernelGGL(k_pchol, dim3(1), dim3(PC_NT), 0, s, G, b, n0, r11sq,
                        rank_tol2, rel2, pivot, T, rank, work);

@@ -56,8 +56,17 @@ struct FineLaunch {
 // Output columns per workgroup of the fused step kernel with nt threads:
 // the three stages consume a halo of 15 columns (3 on the upwind side and
 // 2 on the other, per stage).
-inline int fine_tile_cols(int nt) { return nt - 15; }
-bool fine_nt_supported(int nt);
+// Rows of nx in {128, 256, 512} can be spanned by one workgroup (nt = nx):
+// the full-row variant has no x-halo.
+bool fine_full_row(int nx);
+// Output columns of one workgroup of nt threads on rows of nx points.
+inline int fine_tile_cols(int nt, int nx) {
+  return (nt == nx && fine_full_row(nx)) ? nt : nt - 15;
+}
+bool fine_nt_supported(int nt, int nx);
+// Workgroups of the fused step kernel with nt threads that one compute unit
+// holds at once (registers and LDS), 0 if unknown.
+int fine_blocks_per_cu(int nt, int nx, int sgn);
 
 // One fused RK-3 step for every job (all three stages in one pass over the
 // data, z-marching with LDS row rings).  sgn = +1 for U >= 0, -1 for U < 0.

@@ -421,7 +421,8 @@ bool pr_server::sweep_tick() {
         j.nx = c->g.nx;
         j.nz = c->g.nz;
         j.nslices = a->ns;
-        j.xtiles = (c->g.nx + fine_tile_cols(kServerNT) - 1) / fine_tile_cols(kServerNT);
+        j.xtiles = (c->g.nx + fine_tile_cols(kServerNT, c->g.nx) - 1) /
+                   fine_tile_cols(kServerNT, c->g.nx);
         j.ztiles = (c->g.nz + kServerZC - 1) / kServerZC;
         j.block_begin = blocks;
         j.c = c->fc;

@@ -112,8 +112,9 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
   if (!(o->nu_f >= 0) || !(o->nu_c >= 0)) return fail("nu_f, nu_c must be >= 0");
   if (!(o->rank_tol > 0) || !(o->rank_tol < 1)) return fail("rank_tol must be in (0, 1)");
   if (o->form < 0 || o->form > PR_FORM_STAGEWISE) return fail("unknown form");
-  if (o->tile_nt && !fine_nt_supported(o->tile_nt))
-    return fail("tile_nt must be 0, 128, 192 or 256");
+  if (o->tile_nt && !fine_nt_supported(o->tile_nt, g->nx))
+    return fail("tile_nt must be 0, 128, 192, 256, or nx when nx is 128, "
+                "256 or 512");
   if (o->tile_zc < 0 || o->tile_zc > 4096 || (o->tile_zc % 4))
     return fail("tile_zc must be a multiple of 4 in [0, 4096]");
   const double slice = g->T / P;
@@ -313,7 +314,8 @@ static void fill_job(const pr_ctx* c, FineJob* j, const double* in, int64_t is,
   j->nx = c->g.nx;
   j->nz = c->g.nz;
   j->nslices = ns;
-  j->xtiles = (c->g.nx + fine_tile_cols(nt) - 1) / fine_tile_cols(nt);
+  const int tc = fine_tile_cols(nt, c->g.nx);
+  j->xtiles = (c->g.nx + tc - 1) / tc;
   j->ztiles = (c->g.nz + zc - 1) / zc;
   j->block_begin = block_begin;
   j->c = c->fc;
@@ -359,8 +361,14 @@ int prh::autotune(pr_ctx* c, int ns) {
   }
   RC(ensure_arena(c, ns, 1));
   if (ns > c->P + 1) return PR_OK;
-  static const int nts[] = {128, 192, 256};
+  std::vector<int> nts = {128, 192, 256};
+  if (fine_full_row(c->g.nx) &&
+      std::find(nts.begin(), nts.end(), c->g.nx) == nts.end())
+    nts.push_back(c->g.nx);  // one workgroup per row, no x-halo
   static const int zcs[] = {12, 20, 28, 32, 60, 64, 124, 128, 252};
+  int ncu = 0;
+  HC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                           c->device));
   hipEvent_t e0, e1;
   HC(hipEventCreate(&e0));
   HC(hipEventCreate(&e1));
@@ -369,7 +377,24 @@ int prh::autotune(pr_ctx* c, int ns) {
   const int zmax = std::max(16, (c->g.nz + 15) / 16 * 16);
   for (int nt : nts) {
     if (c->o.tile_nt && nt != c->o.tile_nt) continue;
-    for (int zc : zcs) {
+    // Besides the fixed list, the chunk heights whose workgroup count fills
+    // whole rounds of the machine (m rounds of ncu * blocks-per-CU): a
+    // partial last round leaves compute units idle for a whole chunk.
+    std::vector<int> cand(zcs, zcs + sizeof zcs / sizeof zcs[0]);
+    const int bpc = fine_blocks_per_cu(nt, c->g.nx, c->sgn);
+    const int tc = fine_tile_cols(nt, c->g.nx);
+    const int64_t strips = (int64_t)ns * ((c->g.nx + tc - 1) / tc);
+    for (int m = 1; m <= 4 && bpc > 0; ++m) {
+      const int64_t nch = (int64_t)m * ncu * bpc / strips;
+      if (nch < 1) continue;
+      const int z = (int)((c->g.nz + nch - 1) / nch);
+      const int r4 = (z + 3) / 4 * 4;          // multiple of 4
+      const int r8 = (z + 3) / 8 * 8 + 4;      // 4 mod 8: zc + 12 fills the unroll
+      for (int zc : {r4, r8})
+        if (zc >= 8 && std::find(cand.begin(), cand.end(), zc) == cand.end())
+          cand.push_back(zc);
+    }
+    for (int zc : cand) {
       if (c->o.tile_zc && zc != c->o.tile_zc) continue;
       if (zc > zmax && zc != 12) continue;
       HC(fine_step_launch(c, c->Q, c->ld, c->Qt, c->ld, ns, nt, zc));

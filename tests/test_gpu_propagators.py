@@ -56,6 +56,27 @@ def test_fine_forms_and_tiles_agree(nx, nz, U):
     assert rel_l2(stw, ref) <= TOL_SWEEP
 
 
+@pytest.mark.parametrize("nx,nz", [(128, 24), (256, 13), (512, 12)])
+@pytest.mark.parametrize("U", [0.1, -0.25])
+def test_fine_full_row_tiles(nx, nz, U):
+    """One workgroup per periodic row (tile_nt = nx, no x-halo): parity with
+    the oracle, and bitwise agreement with the halo tiles and with every
+    chunk height, including a ragged last chunk."""
+    prob = small_problem(nx, nz, 3, U=U)
+    Q = rand_states(prob, 3, seed=nx + nz)
+    say(f"full-row {nx}x{nz} U={U}")
+    ref = binding.Context.from_problem(prob, tile_nt=192,
+                                       tile_zc=8).fine_sweep(Q)
+    prm = Params(**prob)
+    for s in range(3):
+        assert rel_l2(ref[s], oracle.fine_F(Q[s], prm)) <= TOL_SWEEP, s
+    for zc in (4, 8, 12, 20, 32):
+        say(f"  tile {nx}x{zc}")
+        got = binding.Context.from_problem(prob, tile_nt=nx,
+                                           tile_zc=zc).fine_sweep(Q)
+        assert np.array_equal(got, ref), zc
+
+
 def test_fine_sweep_device_tensors():
     torch = pytest.importorskip("torch")
     prob = small_problem(64, 32, 2, U=0.1)

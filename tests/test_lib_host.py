@@ -111,6 +111,7 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(dt_g=0.0), "time steps"),
     (dict(n_sound=0), "n_sound"),
     (dict(tile_nt=100), "tile_nt"),
+    (dict(tile_nt=512), "tile_nt"),
     (dict(tile_zc=10), "tile_zc"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
