@@ -53,6 +53,33 @@ __device__ __forceinline__ Coef load_coef(const FineCoef& c) {
               c.cx4,    c.cz4,    c.kxx,    c.kxzu,   c.kzz,    c.kxzw};
 }
 
+// Coefficients of the fused kernel with the damping terms that lie on the
+// advection stencil folded in: the x-damping of u, kxx (u(i+1) - 2 u(i) +
+// u(i-1)), joins the upwind weights of u at offsets -1, 0, +1, and the
+// centre part -2 kzz w of the z-damping of w joins the centre weight of w.
+struct FusedCoef {
+  double a0, a1, a2, a3, a4, a5;  // upwind weights
+  double um, uc, up;   // weights of u at offsets -1, 0, +1 with kxx folded in
+  double wc;           // centre weight of w with -2 kzz folded in
+  double cx4, cz4, kxzu, kzz, kxzw;
+};
+
+template <int SGN>
+__device__ __forceinline__ FusedCoef load_fused_coef(const FineCoef& c) {
+  FusedCoef k;
+  k.a0 = c.adv[0]; k.a1 = c.adv[1]; k.a2 = c.adv[2];
+  k.a3 = c.adv[3]; k.a4 = c.adv[4]; k.a5 = c.adv[5];
+  // weight index of offset 0: 3 for offsets -3 .. +2, 2 for -2 .. +3
+  const double am = SGN > 0 ? k.a2 : k.a1, ac = SGN > 0 ? k.a3 : k.a2,
+               ap = SGN > 0 ? k.a4 : k.a3;
+  k.um = am + c.kxx;
+  k.uc = ac - 2.0 * c.kxx;
+  k.up = ap + c.kxx;
+  k.wc = ac - 2.0 * c.kzz;
+  k.cx4 = c.cx4; k.cz4 = c.cz4; k.kxzu = c.kxzu; k.kzz = c.kzz; k.kxzw = c.kxzw;
+  return k;
+}
+
 // Values a stage carries from row to row (registers): the x-neighbours
 // i-1, i+1 of u and w on the row r about to be computed, and the centred
 // x-differences D_u = u(i+1) - u(i-1), D_w = w(i+1) - w(i-1) on rows r - 1
@@ -92,8 +119,8 @@ template <int SGN>
 __device__ __forceinline__ void rhs_point(
     const double* rc, const Carry& cy, double dup, double dwp,
     double u0, double wm2, double wm1, double w0, double wp1, double wp2,
-    double pm2, double pm1, double p0, double pp1, double pp2, const Coef& k,
-    double& fu, double& fw, double& fp) {
+    double pm2, double pm1, double p0, double pp1, double pp2,
+    const FusedCoef& k, double& fu, double& fw, double& fp) {
   // field f at x-offset dx
   auto U = [&](int dx) { return rc[dx * CS]; };
   auto Wr = [&](int dx) { return rc[dx * CS + 1]; };
@@ -104,16 +131,16 @@ __device__ __forceinline__ void rhs_point(
   const double pxm2 = Pr(-2), pxm1 = Pr(-1), pxp1 = Pr(1), pxp2 = Pr(2);
   double au, aw, ap;
   if (SGN > 0) {  // offsets -3 .. +2
-    au = k.a0 * U(-3) + k.a1 * um2 + k.a2 * um1 + k.a3 * u0 + k.a4 * up1 +
+    au = k.a0 * U(-3) + k.a1 * um2 + k.um * um1 + k.uc * u0 + k.up * up1 +
          k.a5 * up2;
-    aw = k.a0 * Wr(-3) + k.a1 * wxm2 + k.a2 * wxm1 + k.a3 * w0 +
+    aw = k.a0 * Wr(-3) + k.a1 * wxm2 + k.a2 * wxm1 + k.wc * w0 +
          k.a4 * wxp1 + k.a5 * wxp2;
     ap = k.a0 * Pr(-3) + k.a1 * pxm2 + k.a2 * pxm1 + k.a3 * p0 +
          k.a4 * pxp1 + k.a5 * pxp2;
   } else {  // offsets -2 .. +3
-    au = k.a0 * um2 + k.a1 * um1 + k.a2 * u0 + k.a3 * up1 + k.a4 * up2 +
+    au = k.a0 * um2 + k.um * um1 + k.uc * u0 + k.up * up1 + k.a4 * up2 +
          k.a5 * U(3);
-    aw = k.a0 * wxm2 + k.a1 * wxm1 + k.a2 * w0 + k.a3 * wxp1 + k.a4 * wxp2 +
+    aw = k.a0 * wxm2 + k.a1 * wxm1 + k.wc * w0 + k.a3 * wxp1 + k.a4 * wxp2 +
          k.a5 * Wr(3);
     ap = k.a0 * pxm2 + k.a1 * pxm1 + k.a2 * p0 + k.a3 * pxp1 + k.a4 * pxp2 +
          k.a5 * Pr(3);
@@ -122,10 +149,8 @@ __device__ __forceinline__ void rhs_point(
   const double dz4p = (pm2 - pp2) + 8.0 * (pp1 - pm1);
   const double dx4u = (um2 - up2) + 8.0 * (up1 - um1);
   const double dz4w = (wm2 - wp2) + 8.0 * (wp1 - wm1);
-  fu = au - k.cx4 * dx4p + k.kxx * ((up1 + um1) - 2.0 * u0) +
-       k.kxzu * (dwp - cy.dwm);
-  fw = aw - k.cz4 * dz4p + k.kzz * ((wp1 + wm1) - 2.0 * w0) +
-       k.kxzw * (dup - cy.dum);
+  fu = au - k.cx4 * dx4p + k.kxzu * (dwp - cy.dwm);
+  fw = aw - k.cz4 * dz4p + k.kzz * (wp1 + wm1) + k.kxzw * (dup - cy.dum);
   fp = ap - k.cx4 * dx4u - k.cz4 * dz4w;
 }
 
@@ -137,7 +162,7 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
   constexpr int TX = FULL ? NT : NT - 15;
   constexpr int PAD = 3;
   constexpr int W = NT + 2 * PAD;
-  static_assert(8 % PF == 0, "prefetch depth must divide the unroll");
+  static_assert(4 % PF == 0, "prefetch depth must divide the 4-row tail");
   __shared__ double ring[W * CS];  // column-major, see CS
 
   const int lb = xcd_logical_block(L.nblocks);
@@ -156,7 +181,7 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
   const int64_t n = (int64_t)nx * nz;
   const double* __restrict__ in = J.in + sl * J.in_stride;
   double* __restrict__ out = J.out + sl * J.out_stride;
-  const Coef k = load_coef(J.c);
+  const FusedCoef k = load_fused_coef<SGN>(J.c);
   const double dt = J.c.dt;
   const double b1 = dt / 3.0, b2 = 0.5 * dt;
 
@@ -215,8 +240,10 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
   // advances the carry; DOL computes the row.  All flags are compile-time
   // after unrolling, so in the steady state the three stages (which read
   // only rows produced in earlier iterations) are straight-line code the
-  // scheduler interleaves.  Rows past the chunk (it >= nrows) are computed
-  // and discarded, so the row count need not be a multiple of the unroll.
+  // scheduler interleaves.  The row count zc + 12 is a multiple of 4: whole
+  // blocks of 8 rows, then at most one block of 4.  The prefetch never
+  // reaches past the chunk's last input row (it re-reads that row, which is
+  // still in cache).
 #define PR_STAGE(PRE, DO, LVL, CY, ZU, ZW, ZP, BU, BW, BP, OU, OW, OP, BETA, STORE) \
   if (PRE) {                                                                  \
     double xum, xup, xwm, xwp;                                                \
@@ -253,7 +280,8 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
       iw[uu] = fw_[q];                                                        \
       ip[uu] = fp_[q];                                                        \
       ring_put(slot(0, (uu) & 3), iu[uu], iw[uu], ip[uu]);                    \
-      const double* src = in + (int64_t)wrap(z0 - 6 + (it) + PF, nz) * nx + gx; \
+      const int zp = (it) + PF < nrows ? (it) + PF : nrows - 1;               \
+      const double* src = in + (int64_t)wrap(z0 - 6 + zp, nz) * nx + gx;      \
       fu_[q] = src[0];                                                        \
       fw_[q] = src[n];                                                        \
       fp_[q] = src[2 * n];                                                    \
@@ -285,9 +313,15 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
 #pragma unroll
   for (int uu = 0; uu < 8; ++uu)
     PR_ROW(uu, 8 + uu, true, true, true, true, uu >= 2, uu >= 4)
-  for (int base = 16; base < nrows; base += 8) {
+  int base = 16;
+  for (; base + 8 <= nrows; base += 8) {
 #pragma unroll
     for (int uu = 0; uu < 8; ++uu)
+      PR_ROW(uu, base + uu, true, true, true, true, true, true)
+  }
+  if (base < nrows) {
+#pragma unroll
+    for (int uu = 0; uu < 4; ++uu)
       PR_ROW(uu, base + uu, true, true, true, true, true, true)
   }
 #undef PR_ROW
@@ -348,11 +382,15 @@ __global__ __launch_bounds__(256) void k_fine_stage(
   O[2 * n + idx] = B[2 * n + idx] + beta * fp;
 }
 
+// Prefetch depth in rows: the halo variants hold more per-thread state and
+// stay within 256 VGPRs only with 2.
+constexpr int fine_pf(bool full) { return full ? 4 : 2; }
+
 template <int SGN, int NT, bool FULL>
 hipError_t launch_nt(const FineLaunch& L, hipStream_t s) {
   const int grid = 8 * ((L.nblocks + 7) / 8);
-  hipLaunchKernelGGL((k_fine_step<SGN, NT, 4, FULL>), dim3(grid), dim3(NT), 0,
-                     s, L);
+  hipLaunchKernelGGL((k_fine_step<SGN, NT, fine_pf(FULL), FULL>), dim3(grid),
+                     dim3(NT), 0, s, L);
   return hipGetLastError();
 }
 
@@ -378,7 +416,8 @@ template <int SGN, int NT, bool FULL>
 int blocks_per_cu() {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void*>(&k_fine_step<SGN, NT, 4, FULL>),
+          &nb,
+          reinterpret_cast<const void*>(&k_fine_step<SGN, NT, fine_pf(FULL), FULL>),
           NT, 0) != hipSuccess)
     return 0;
   return nb;

@@ -18,9 +18,10 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int GEMV_NT = 256;
-constexpr int GEMV_E = 8;   // elements of x per thread
+constexpr int GEMV_E = 8;   // elements of x per thread (column norms)
 constexpr int GEMV_JG = 8;  // columns per workgroup
 constexpr int GEMV_CHUNK = GEMV_NT * GEMV_E;
+constexpr int GEMV_RESIDENT = 256;  // workgroups of one projection launch
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -44,33 +45,46 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// c = V^T x, partial sums: blockIdx.x picks a chunk of GEMV_CHUNK elements
-// of x, blockIdx.y a group of GEMV_JG columns; each thread keeps its
-// GEMV_E elements of x in registers and accumulates GEMV_JG dot products,
-// reduced across the workgroup once per group.
+// c = V^T x, partial sums.  One workgroup per (group of GEMV_JG columns,
+// slice of d) item, with few enough items (about one workgroup per compute
+// unit) that the grid stays resident beside a concurrent coarse step, which
+// then finds its compute units free.  Each thread keeps four elements of x
+// and 4 * GEMV_JG column loads in flight and reduces once at the end:
+// part[slice * ncols + j] = sum over the slice of V[j][x] x[x].
 __global__ __launch_bounds__(GEMV_NT) void k_gemv_t(
     const double* __restrict__ V, int64_t ld, int ncols,
-    const double* __restrict__ x, int64_t d, double* __restrict__ part) {
+    const double* __restrict__ x, int64_t d, int nsl, int64_t len,
+    double* __restrict__ part) {
   __shared__ double sh[GEMV_JG][GEMV_NT / 64];
-  const int64_t x0 = (int64_t)blockIdx.x * GEMV_CHUNK;
-  const int j0 = blockIdx.y * GEMV_JG;
-  double xv[GEMV_E];
+  const int grp = blockIdx.x / nsl, sl = blockIdx.x % nsl;
+  const int j0 = grp * GEMV_JG;
+  const int64_t xs = (int64_t)sl * len;
+  const int64_t xe = xs + len < d ? xs + len : d;
+  const double* col[GEMV_JG];
 #pragma unroll
-  for (int e = 0; e < GEMV_E; ++e) {
-    const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
-    xv[e] = i < d ? x[i] : 0.0;
-  }
+  for (int q = 0; q < GEMV_JG; ++q)
+    col[q] = V + (int64_t)(j0 + q < ncols ? j0 + q : ncols - 1) * ld;
   double acc[GEMV_JG];
 #pragma unroll
-  for (int q = 0; q < GEMV_JG; ++q) {
-    acc[q] = 0.0;
-    const int j = j0 + q < ncols ? j0 + q : ncols - 1;
-    const double* col = V + (int64_t)j * ld;
+  for (int q = 0; q < GEMV_JG; ++q) acc[q] = 0.0;
+  int64_t i = xs + threadIdx.x;
+  for (; i + 3 * GEMV_NT < xe; i += 4 * GEMV_NT) {
+    double xv[4];
 #pragma unroll
-    for (int e = 0; e < GEMV_E; ++e) {
-      const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
-      if (i < d) acc[q] += col[i] * xv[e];
+    for (int u = 0; u < 4; ++u) xv[u] = x[i + u * GEMV_NT];
+#pragma unroll
+    for (int q = 0; q < GEMV_JG; ++q) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = col[q][i + u * GEMV_NT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[q] += v[u] * xv[u];
     }
+  }
+  for (; i < xe; i += GEMV_NT) {
+    const double xv = x[i];
+#pragma unroll
+    for (int q = 0; q < GEMV_JG; ++q) acc[q] += col[q][i] * xv;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -80,10 +94,10 @@ __global__ __launch_bounds__(GEMV_NT) void k_gemv_t(
   }
   __syncthreads();
   if (threadIdx.x < GEMV_JG && j0 + (int)threadIdx.x < ncols) {
-    double s = 0.0;
+    double sacc = 0.0;
 #pragma unroll
-    for (int w = 0; w < GEMV_NT / 64; ++w) s += sh[threadIdx.x][w];
-    part[(int64_t)blockIdx.x * ncols + j0 + threadIdx.x] = s;
+    for (int w = 0; w < GEMV_NT / 64; ++w) sacc += sh[threadIdx.x][w];
+    part[(int64_t)sl * ncols + j0 + threadIdx.x] = sacc;
   }
 }
 
@@ -202,6 +216,64 @@ __global__ __launch_bounds__(COMB_NT) void k_combine(
       q[i] = nw;
     } else {
       q[i] = k;
+    }
+  }
+}
+
+// out = g + sum_j D[j] c[j], with the per-element association of
+// k_combine and a resident grid: workgroup b owns elements
+// [b*len, (b+1)*len) and each thread four elements per pass, eight basis
+// vectors per inner step (32 loads in flight).
+__global__ __launch_bounds__(COMB_NT) void k_lincomb(
+    double* __restrict__ out, const double* __restrict__ g,
+    const double* __restrict__ D, int64_t ld, int ncols,
+    const double* __restrict__ c, int64_t d, int64_t len) {
+  __shared__ double cs[COMB_MAXC];
+  for (int j = threadIdx.x; j < ncols; j += COMB_NT) cs[j] = c[j];
+  __syncthreads();
+  const int64_t xs = (int64_t)blockIdx.x * len;
+  const int64_t xe = xs + len < d ? xs + len : d;
+  for (int64_t x0 = xs + threadIdx.x; x0 < xe; x0 += 4 * COMB_NT) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = 0;
+    for (; j + 8 <= ncols; j += 8) {
+      const double* d0 = D + (int64_t)j * ld;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = x0 + e * COMB_NT;
+        if (i < xe) {
+          double v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = d0[(int64_t)q * ld + i];
+          acc[e] += ((v[0] * cs[j] + v[1] * cs[j + 1]) +
+                     (v[2] * cs[j + 2] + v[3] * cs[j + 3])) +
+                    ((v[4] * cs[j + 4] + v[5] * cs[j + 5]) +
+                     (v[6] * cs[j + 6] + v[7] * cs[j + 7]));
+        }
+      }
+    }
+    for (; j + 4 <= ncols; j += 4) {
+      const double* d0 = D + (int64_t)j * ld;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = x0 + e * COMB_NT;
+        if (i < xe)
+          acc[e] += (d0[i] * cs[j] + d0[ld + i] * cs[j + 1]) +
+                    (d0[2 * ld + i] * cs[j + 2] + d0[3 * ld + i] * cs[j + 3]);
+      }
+    }
+    for (; j < ncols; ++j) {
+      const double* d0 = D + (int64_t)j * ld;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t i = x0 + e * COMB_NT;
+        if (i < xe) acc[e] += d0[i] * cs[j];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = x0 + e * COMB_NT;
+      if (i < xe) out[i] = (g ? g[i] : 0.0) + acc[e];
     }
   }
 }
@@ -684,13 +756,35 @@ __global__ void k_small_matmul(const double* __restrict__ T1, int b, int rho1,
 
 int gemv_t_blocks(int64_t d) { return (int)((d + GEMV_CHUNK - 1) / GEMV_CHUNK); }
 
+namespace {
+// Slices of d for a projection onto ncols vectors: about GEMV_RESIDENT
+// workgroups in all, each slice at least GEMV_CHUNK elements.
+int gemv_slices(int64_t d, int ncols) {
+  const int ngrp = (ncols + GEMV_JG - 1) / GEMV_JG;
+  int nsl = GEMV_RESIDENT / ngrp;
+  const int64_t cap = (d + GEMV_CHUNK - 1) / GEMV_CHUNK;
+  if (nsl > cap) nsl = (int)cap;
+  return nsl < 1 ? 1 : nsl;
+}
+}  // namespace
+
+size_t gemv_t_part(int64_t d, int ncols) {
+  return (size_t)gemv_slices(d, ncols) * (size_t)(ncols > 0 ? ncols : 0);
+}
+
 hipError_t launch_gemv_t(const double* V, int64_t ld, int ncols,
-                         const double* x, int64_t d, double* part, int nblk,
+                         const double* x, int64_t d, double* part, double* c,
                          hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemv_t, dim3(nblk, (ncols + GEMV_JG - 1) / GEMV_JG),
-                     dim3(GEMV_NT), 0, s, V, ld, ncols, x, d, part);
-  return hipGetLastError();
+  const int nsl = gemv_slices(d, ncols);
+  const int ngrp = (ncols + GEMV_JG - 1) / GEMV_JG;
+  int64_t len = (d + nsl - 1) / nsl;
+  len = (len + GEMV_NT - 1) / GEMV_NT * GEMV_NT;
+  hipLaunchKernelGGL(k_gemv_t, dim3(ngrp * nsl), dim3(GEMV_NT), 0, s, V, ld,
+                     ncols, x, d, nsl, len, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_reduce_cols(part, nsl, ncols, c, s);
 }
 
 hipError_t launch_reduce_cols(const double* part, int nblk, int ncols,
@@ -729,10 +823,16 @@ hipError_t launch_lincomb(double* out, const double* g, const double* D,
                           int64_t ld, int ncols, const double* c, int64_t d,
                           hipStream_t s) {
   if (ncols > COMB_MAXC) return hipErrorInvalidValue;
-  const int64_t per = (int64_t)COMB_NT * COMB_E;
-  hipLaunchKernelGGL(k_combine<1>, dim3((unsigned)((d + per - 1) / per)),
-                     dim3(COMB_NT), 0, s, out, (double*)nullptr,
-                     (const double*)nullptr, g, D, ld, ncols, c, d);
+  if (d <= 0) return hipSuccess;
+  // About GEMV_RESIDENT workgroups (see k_gemv_t), at least 1024 elements
+  // each.
+  int64_t nb = (d + 1023) / 1024;
+  if (nb > GEMV_RESIDENT) nb = GEMV_RESIDENT;
+  int64_t len = (d + nb - 1) / nb;
+  len = (len + COMB_NT - 1) / COMB_NT * COMB_NT;
+  nb = (d + len - 1) / len;
+  hipLaunchKernelGGL(k_lincomb, dim3((unsigned)nb), dim3(COMB_NT), 0, s, out,
+                     g, D, ld, ncols, c, d, len);
   return hipGetLastError();
 }
 

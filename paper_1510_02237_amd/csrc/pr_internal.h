@@ -118,11 +118,14 @@ hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s);
 // length d is stored vector after vector: V[j*ld + x].
 // ---------------------------------------------------------------------------
 
-// Partial inner products for c = V^T x over nblk chunks of d (deterministic):
-// part[b*ncols + j] = sum over chunk b of V[j][x] x[x].
+// Chunks of d used by the column-norm partials (launch_colnorm2).
 int gemv_t_blocks(int64_t d);
+// c = V^T x (deterministic: fixed slices of d, partial sums in part, summed
+// in a fixed order).  part needs gemv_t_part(d, ncols) doubles, at most
+// max(2048, ncols).
+size_t gemv_t_part(int64_t d, int ncols);
 hipError_t launch_gemv_t(const double* V, int64_t ld, int ncols,
-                         const double* x, int64_t d, double* part, int nblk,
+                         const double* x, int64_t d, double* part, double* c,
                          hipStream_t s);
 // c[j] = sum_b part[b*ncols + j] in a fixed order.
 hipError_t launch_reduce_cols(const double* part, int nblk, int ncols,

@@ -237,6 +237,8 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
   if (changed) {
     const int m = std::max(c->wcap, c->rcap);
     const int w = c->wcap;
+    // Partials: column norms use gemv_t_blocks(ld) per column, projections
+    // at most as many (their slice count is capped by it).
     const size_t nblk = (size_t)gemv_t_blocks(c->ld);
     size_t off = 0;
     const size_t part = nblk * m, cvec = m, cm = (size_t)c->rcap * w,
@@ -361,10 +363,12 @@ int prh::autotune(pr_ctx* c, int ns) {
   }
   RC(ensure_arena(c, ns, 1));
   if (ns > c->P + 1) return PR_OK;
-  std::vector<int> nts = {128, 192, 256};
-  if (fine_full_row(c->g.nx) &&
-      std::find(nts.begin(), nts.end(), c->g.nx) == nts.end())
-    nts.push_back(c->g.nx);  // one workgroup per row, no x-halo
+  // One workgroup per row (no x-halo, the least traffic) is tried first, so
+  // that a halo tile has to beat it clearly to be chosen.
+  std::vector<int> nts;
+  if (fine_full_row(c->g.nx)) nts.push_back(c->g.nx);
+  for (int nt : {128, 192, 256})
+    if (std::find(nts.begin(), nts.end(), nt) == nts.end()) nts.push_back(nt);
   static const int zcs[] = {12, 20, 28, 32, 60, 64, 124, 128, 252};
   int ncu = 0;
   HC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
@@ -408,9 +412,9 @@ int prh::autotune(pr_ctx* c, int ns) {
         HC(hipEventElapsedTime(&one, e0, e1));
         ms = std::min(ms, one);
       }
-      // A later candidate must win by 2% to displace an earlier one, which
+      // A later candidate must win by 3% to displace an earlier one, which
       // keeps the choice stable against timing noise.
-      if (ms < 0.98f * best) {
+      if (ms < 0.97f * best) {
         best = ms;
         bnt = nt;
         bzc = zc;
@@ -663,7 +667,6 @@ int prh::chain(pr_ctx* c, int k) {
   HC(launch_combine(c->Q + (int64_t)(k + 1) * ld, k + 1 < P ? da : nullptr,
                     c->Qt + (int64_t)(k + 1) * ld, nullptr, nullptr, ld, 0,
                     nullptr, d, s));
-  const int nblk = gemv_t_blocks(d);
   double* y = single(c, kY);
   for (int i = k + 1; i < P; ++i) {
     // K(delta) = G(delta) + D(S) (S^T delta): the fine part (two passes over
@@ -672,8 +675,7 @@ int prh::chain(pr_ctx* c, int k) {
     if (c->r > 0) {
       HC(hipEventRecord(c->ev_fork, s));
       HC(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-      HC(launch_gemv_t(c->S, ld, c->r, da, d, c->part, nblk, c->side));
-      HC(launch_reduce_cols(c->part, nblk, c->r, c->cvec, c->side));
+      HC(launch_gemv_t(c->S, ld, c->r, da, d, c->part, c->cvec, c->side));
       HC(launch_lincomb(y, nullptr, c->D, ld, c->r, c->cvec, d, c->side));
       HC(hipEventRecord(c->ev_join, c->side));
     }
@@ -967,9 +969,7 @@ extern "C" int pr_coarse_step(pr_ctx* c, const double* q, double* gq,
   RC(copy_state_in(c, io, q, mem));
   RC(run_coarse(c, io, g, 1, c->ld, single(c, kTa), single(c, kTb), single(c, kRs)));
   if (use_krylov && c->r > 0) {
-    const int nblk = gemv_t_blocks(c->d);
-    HC(launch_gemv_t(c->S, c->ld, c->r, io, c->d, c->part, nblk, c->stream));
-    HC(launch_reduce_cols(c->part, nblk, c->r, c->cvec, c->stream));
+    HC(launch_gemv_t(c->S, c->ld, c->r, io, c->d, c->part, c->cvec, c->stream));
     HC(launch_lincomb(g, g, c->D, c->ld, c->r, c->cvec, c->d, c->stream));
   }
   RC(copy_state_out(c, gq, g, mem));
