@@ -21,7 +21,8 @@ constexpr int GEMV_NT = 256;
 constexpr int GEMV_E = 8;   // elements of x per thread (column norms)
 constexpr int GEMV_JG = 8;  // columns per workgroup
 constexpr int GEMV_CHUNK = GEMV_NT * GEMV_E;
-constexpr int GEMV_RESIDENT = 256;  // workgroups of one projection launch
+constexpr int GEMV_RESIDENT = 256;  // workgroups of one c = V^T x launch
+constexpr int LINCOMB_RESIDENT = 512;  // workgroups of one D c launch
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -824,10 +825,10 @@ hipError_t launch_lincomb(double* out, const double* g, const double* D,
                           hipStream_t s) {
   if (ncols > COMB_MAXC) return hipErrorInvalidValue;
   if (d <= 0) return hipSuccess;
-  // About GEMV_RESIDENT workgroups (see k_gemv_t), at least 1024 elements
-  // each.
+  // About LINCOMB_RESIDENT workgroups (few enough to stay resident, see
+  // k_gemv_t; enough loads in flight), at least 1024 elements each.
   int64_t nb = (d + 1023) / 1024;
-  if (nb > GEMV_RESIDENT) nb = GEMV_RESIDENT;
+  if (nb > LINCOMB_RESIDENT) nb = LINCOMB_RESIDENT;
   int64_t len = (d + nb - 1) / nb;
   len = (len + COMB_NT - 1) / COMB_NT * COMB_NT;
   nb = (d + len - 1) / len;
