@@ -99,6 +99,15 @@ typedef struct pr_opts {
                              0 = autotune                                      */
   int32_t tile_zc;        /* fine-sweep output rows per workgroup (multiple of
                              4), 0 = autotune                                  */
+  int32_t windows;        /* parallel steps M_p of Section 2.1: [0, T] is
+                             integrated in `windows` sequential windows of P
+                             slices, each slice T / (windows * P) long; every
+                             window starts from the previous window's final
+                             state with an empty subspace (the initialization
+                             of Algorithm 2).  1 (default) = one window.  With
+                             dt_g = T / (windows * P) every slice is one
+                             coarse step, as in the paper's runs.  The server
+                             accepts only 1.                                   */
 } pr_opts;
 
 typedef struct pr_ctx pr_ctx;

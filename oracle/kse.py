@@ -21,7 +21,9 @@ Readings taken where the paper is silent (also listed with the design notes):
     same as Algorithm 2's K(new) + qt - K(old); it keeps slices that have
     converged bitwise equal to the serial fine run;
   * the iteration count is fixed (no stopping test, Section 2.1);
-  * one window: the P slices cover [0, T].
+  * windows (the parallel steps of Section 2.1) run one after the other,
+    each starting from the previous window's final state q^K_P and, as
+    Algorithm 2's initialization says, from an empty subspace.
 """
 
 import numpy as np
@@ -78,10 +80,36 @@ def _vec(states):
 
 
 def kse_parareal(u0, prm: Params, K, krylov=True, history=False):
-    """Algorithm 2 (or Algorithm 1 with ``krylov=False``, i.e. S = empty).
+    """Algorithm 2 (or Algorithm 1 with ``krylov=False``, i.e. S = empty)
+    over the ``prm.windows`` parallel steps of Section 2.1.
+
+    Returns the last window's dict (see ``_one_window``) with, in addition,
+      window_ends   the final state q^K_P of every window
+      window_ranks  ``ranks`` of every window (krylov only)
+    With one window this is exactly ``_one_window``'s result plus those two
+    entries.
+    """
+    u = np.asarray(u0, dtype=np.float64)
+    ends, wranks = [], []
+    out = None
+    for _ in range(prm.windows):
+        out = _one_window(u, prm, K, krylov=krylov, history=history)
+        u = out["q"][prm.P]
+        ends.append(u)
+        if krylov:
+            wranks.append(out["ranks"])
+    out["window_ends"] = ends
+    if krylov:
+        out["window_ranks"] = wranks
+    return out
+
+
+def _one_window(u0, prm: Params, K, krylov=True, history=False):
+    """One parallel step of Algorithm 2 (Algorithm 1 with ``krylov=False``)
+    on the P slices that start at u0.
 
     Returns a dict:
-      q       list of P+1 states q^K_0..q^K_P (q[P] is the solution at T)
+      q       list of P+1 states q^K_0..q^K_P (q[P] is the window's end)
       ranks   dim S^k after each iteration's update (krylov only)
       diagR   |R_jj| of each iteration's pivoted QR (krylov only)
       S, FS   the last basis and its fine images (krylov only)

@@ -35,8 +35,11 @@ class Params:
     nx, nz      cells along x and z (dx = Lx/nx, dz = Lz/nz)
     c_s, U      sound speed and constant advection velocity along x
     dt_f, dt_g  fine step (delta t) and coarse step (Delta t)
-    P           number of time slices N_c (one window covering [0, T])
+    P           number of time slices N_c of one window (parallel step)
     T           end time
+    windows     number of parallel steps M_p (Section 2.1): [0, T] is
+                covered by ``windows`` windows of P slices each, a slice
+                being T / (windows * P) long
     nu_f, nu_c  divergence-damping factors of F and G (eq. dampingCoeff)
     n_sound     acoustic substeps per coarse step (N_sound, Section 3.2)
     rank_tol    relative tolerance on |R_jj|/|R_11| for the rank of the
@@ -58,6 +61,7 @@ class Params:
     rank_tol: float = 1e-10
     Lx: float = 1.0
     Lz: float = 1.0
+    windows: int = 1
 
     @property
     def dx(self):
@@ -72,14 +76,19 @@ class Params:
         return 3 * self.nx * self.nz
 
     @property
+    def slice_length(self):
+        """Length of one time slice, T / (windows * P)."""
+        return self.T / (self.windows * self.P)
+
+    @property
     def n_f(self):
-        """Fine steps per slice, N_f = (T/P)/dt_f (Section 2.1)."""
-        return _integer_ratio(self.T / self.P, self.dt_f)
+        """Fine steps per slice, N_f = slice length / dt_f (Section 2.1)."""
+        return _integer_ratio(self.slice_length, self.dt_f)
 
     @property
     def n_g(self):
-        """Coarse steps per slice, (T/P)/dt_g."""
-        return _integer_ratio(self.T / self.P, self.dt_g)
+        """Coarse steps per slice, slice length / dt_g."""
+        return _integer_ratio(self.slice_length, self.dt_g)
 
 
 def _integer_ratio(a, b):

@@ -55,9 +55,9 @@ def coarse_G(q, prm: Params, nsteps=None):
 
 
 def serial_fine(u0, prm: Params, nslices=None):
-    """Reference run of F sequentially over ``nslices`` (default P) slices,
-    i.e. q_seq of eq. errorDef at t = T."""
+    """Reference run of F sequentially over ``nslices`` slices (default all
+    windows * P of them), i.e. q_seq of eq. errorDef at t = T."""
     q = np.array(u0, dtype=np.float64, copy=True)
-    for _ in range(prm.P if nslices is None else nslices):
+    for _ in range(prm.windows * prm.P if nslices is None else nslices):
         q = fine_F(q, prm)
     return q

@@ -42,7 +42,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("nu_f", ctypes.c_double), ("nu_c", ctypes.c_double),
                 ("n_sound", ctypes.c_int32), ("rank_tol", ctypes.c_double),
                 ("form", ctypes.c_int32), ("skip_converged", ctypes.c_int32),
-                ("tile_nt", ctypes.c_int32), ("tile_zc", ctypes.c_int32)]
+                ("tile_nt", ctypes.c_int32), ("tile_zc", ctypes.c_int32),
+                ("windows", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -221,7 +222,8 @@ class Context:
     def from_problem(cls, prob, **opts):
         """From a workload dict (paper_1510_02237_amd.workloads.problem)."""
         o = dict(nu_f=prob["nu_f"], nu_c=prob["nu_c"],
-                 n_sound=prob["n_sound"], rank_tol=prob["rank_tol"])
+                 n_sound=prob["n_sound"], rank_tol=prob["rank_tol"],
+                 windows=prob.get("windows", 1))
         o.update(opts)
         return cls(prob["nx"], prob["nz"], prob["c_s"], prob["U"],
                    prob["dt_f"], prob["dt_g"], prob["P"], T=prob["T"], **o)
@@ -294,7 +296,8 @@ class Context:
         a = _Arg(u0, self.shape)
         out = _like(u0, self.shape) if out is None else out
         o = _Arg(out, self.shape, writable=True)
-        ns = self.P if nslices is None else int(nslices)
+        # default: every slice of every window, i.e. [0, T]
+        ns = self.P * self.opts.windows if nslices is None else int(nslices)
         self._chk(self.lib.pr_serial_fine(self._h, a.ptr, ns, o.ptr, a.mem))
         return out
 

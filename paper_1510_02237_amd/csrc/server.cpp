@@ -506,6 +506,8 @@ extern "C" int pr_submit_ex(pr_server* s, const pr_grid* g, double c_s,
   pr_opts_default(&def);
   if (!o) o = &def;
   if (K < 0) return set_serr(s, PR_EINVAL, "K must be >= 0");
+  if (o->windows != 1)
+    return set_serr(s, PR_EINVAL, "the server solves one window (windows = 1)");
   int nf, ng;
   std::string msg;
   int rc = pr_validate(g, c_s, U, dt_f, dt_g, P, o, &nf, &ng, &msg);

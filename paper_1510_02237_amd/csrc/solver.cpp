@@ -88,6 +88,7 @@ extern "C" void pr_opts_default(pr_opts* o) {
   o->skip_converged = 1;
   o->tile_nt = 0;
   o->tile_zc = 0;
+  o->windows = 1;
 }
 
 // Validates the problem; fills n_f, n_g.  Shared with the server.
@@ -117,13 +118,17 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
                 "256 or 512");
   if (o->tile_zc < 0 || o->tile_zc > 4096 || (o->tile_zc % 4))
     return fail("tile_zc must be a multiple of 4 in [0, 4096]");
-  const double slice = g->T / P;
+  if (o->windows < 1 || o->windows > (1 << 20))
+    return fail("windows must be in [1, 2^20]");
+  const double slice = g->T / ((double)o->windows * P);
   if (int_ratio(slice, dt_f, nf)) {
-    snprintf(buf, sizeof buf, "(T/P)/dt_f = %.17g is not an integer", slice / dt_f);
+    snprintf(buf, sizeof buf, "(T/(windows*P))/dt_f = %.17g is not an integer",
+             slice / dt_f);
     return fail(buf);
   }
   if (int_ratio(slice, dt_g, ng)) {
-    snprintf(buf, sizeof buf, "(T/P)/dt_g = %.17g is not an integer", slice / dt_g);
+    snprintf(buf, sizeof buf, "(T/(windows*P))/dt_g = %.17g is not an integer",
+             slice / dt_g);
     return fail(buf);
   }
   return PR_OK;
@@ -704,12 +709,12 @@ static int copy_state_out(pr_ctx* c, double* dst, const double* src, int mem) {
   return PR_OK;
 }
 
-static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
-                      double* slices, int mem, bool krylov) {
-  if (!u0 || !U_K) return set_error(c, PR_EINVAL, "null state pointer");
-  if (K < 0) return set_error(c, PR_EINVAL, "K must be >= 0");
-  if (mem != PR_MEM_HOST && mem != PR_MEM_DEVICE)
-    return set_error(c, PR_EINVAL, "bad mem kind");
+// One window (parallel step) of Algorithm 2 (or 1): u0 in memory kind
+// mem_in, or NULL to start from the previous window's final state Q[P];
+// U_K (optional) and slices (optional) in memory kind mem.  The final state
+// stays in Q[P].
+static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
+                        double* U_K, double* slices, int mem, bool krylov) {
   const int P = c->P;
   const int Keff = std::min<int>(K, P);
   const int64_t ld = c->ld;
@@ -737,7 +742,11 @@ static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
   c->r = 0;
   HC(hipMemsetAsync(c->d_r11sq, 0, sizeof(double), s));
   HC(hipMemsetAsync(c->ism + 2, 0, sizeof(int), s));
-  RC(copy_state_in(c, c->Q, u0, mem));
+  if (u0)
+    RC(copy_state_in(c, c->Q, u0, mem_in));
+  else
+    HC(hipMemcpyAsync(c->Q, c->Q + (int64_t)P * ld, (size_t)c->d * 8,
+                      hipMemcpyDeviceToDevice, s));
   HC(hipEventRecord(ev[0], s));
   RC(with_graph(c, gkey(1, 0, 0), [&] { return coarse_init(c); }));
   HC(hipEventRecord(ev[1], s));
@@ -794,7 +803,7 @@ static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
   }
   c->stats.ms_total = el(0, 2 + 3 * Keff);
   c->stats.fine_point_steps = pts;
-  RC(copy_state_out(c, U_K, c->Q + (int64_t)P * ld, mem));
+  if (U_K) RC(copy_state_out(c, U_K, c->Q + (int64_t)P * ld, mem));
   if (slices) {
     HC(hipMemcpy2DAsync(slices, (size_t)c->d * 8, c->Q, (size_t)ld * 8,
                         (size_t)c->d * 8, P + 1,
@@ -803,6 +812,37 @@ static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
                         s));
   }
   HC(hipStreamSynchronize(s));
+  return PR_OK;
+}
+
+// Section 2.1: windows (parallel steps) run one after the other, each from
+// the previous window's final state and with an empty subspace.  Timings
+// and fine point-steps are summed over the windows; ranks are the last
+// window's.
+static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
+                      double* slices, int mem, bool krylov) {
+  if (!u0 || !U_K) return set_error(c, PR_EINVAL, "null state pointer");
+  if (K < 0) return set_error(c, PR_EINVAL, "K must be >= 0");
+  if (mem != PR_MEM_HOST && mem != PR_MEM_DEVICE)
+    return set_error(c, PR_EINVAL, "bad mem kind");
+  const int M = c->o.windows;
+  if (M <= 1) return solve_window(c, u0, mem, K, U_K, slices, mem, krylov);
+  pr_stats acc{};
+  for (int w = 0; w < M; ++w) {
+    const bool last = w == M - 1;
+    RC(solve_window(c, w == 0 ? u0 : nullptr, mem, K,
+                    last ? U_K : nullptr, last ? slices : nullptr, mem,
+                    krylov));
+    acc.ms_total += c->stats.ms_total;
+    acc.ms_coarse_init += c->stats.ms_coarse_init;
+    acc.ms_fine += c->stats.ms_fine;
+    acc.ms_update += c->stats.ms_update;
+    acc.ms_chain += c->stats.ms_chain;
+    acc.fine_point_steps += c->stats.fine_point_steps;
+  }
+  acc.iterations = c->stats.iterations;
+  std::memcpy(acc.rank, c->stats.rank, sizeof acc.rank);
+  c->stats = acc;
   return PR_OK;
 }
 

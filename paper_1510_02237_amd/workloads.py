@@ -38,14 +38,26 @@ def n_sound_for(U):
 
 
 def problem(nx, nz, P, U=0.1, c_s=1.0, T=1.0, cfl_f=0.2, coarse_ratio=10,
-            n_sound=None):
-    """Plain dict of problem parameters shared by the library and the oracle."""
+            n_sound=None, windows=1):
+    """Plain dict of problem parameters shared by the library and the oracle.
+    ``windows`` parallel steps of P slices cover [0, T]."""
     dt_f = cfl_f * min(1.0 / nx, 1.0 / nz) / c_s
     return dict(nx=int(nx), nz=int(nz), c_s=float(c_s), U=float(U),
                 dt_f=dt_f, dt_g=coarse_ratio * dt_f, P=int(P), T=float(T),
                 nu_f=NU_F, nu_c=NU_C,
                 n_sound=int(n_sound if n_sound is not None else n_sound_for(U)),
-                rank_tol=RANK_TOL)
+                rank_tol=RANK_TOL, windows=int(windows))
+
+
+def one_coarse_step_windows(prob):
+    """The window count that makes every slice one coarse step (the paper's
+    runs: N_c = N_p coarse intervals per parallel step, Section 2.1):
+    T / (P * dt_g)."""
+    m = prob["T"] / (prob["P"] * prob["dt_g"])
+    M = int(round(m))
+    if M < 1 or abs(M - m) > 1e-9 * m:
+        raise ValueError("T / (P dt_g) is not an integer")
+    return M
 
 
 def _cell_centres(nx, nz):
@@ -109,6 +121,13 @@ CONFIGS = {
                         ic=dict(kind="bumps", nbumps=4, noise=1e-3)),
     "c5_4096x1024": dict(nx=4096, nz=1024, P=128, K=4, U=0.2, seed=5,
                          ic=dict(kind="fourier", nmodes=32, kmax=64)),
+    # The paper's own time decomposition (Section 2.1): every slice is one
+    # coarse step, [0, T] is covered by T / (P dt_g) windows of P slices.
+    "c1w_64x32": dict(nx=64, nz=32, P=8, K=3, U=0.1, seed=1,
+                      ic=dict(kind="bumps", nbumps=1), windows="one_step"),
+    "c2w_512x256": dict(nx=512, nz=256, P=32, K=4, U=0.1, seed=2,
+                        ic=dict(kind="bumps", nbumps=4, noise=1e-3),
+                        windows="one_step"),
 }
 
 
@@ -116,6 +135,8 @@ def config(name):
     """(problem dict, K, initial state) of a named workload."""
     c = CONFIGS[name]
     prob = problem(c["nx"], c["nz"], c["P"], U=c["U"])
+    if c.get("windows") == "one_step":
+        prob["windows"] = one_coarse_step_windows(prob)
     ic = dict(c["ic"])
     kind = ic.pop("kind")
     if kind == "bumps":

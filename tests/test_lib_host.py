@@ -49,6 +49,7 @@ def test_opts_default(lib):
     assert o.nu_f == 0.005 and o.nu_c == 0.1 and o.n_sound == 4
     assert o.rank_tol == 1e-10 and o.form == binding.PR_FORM_BATCHED
     assert o.skip_converged == 1 and o.tile_nt == 0 and o.tile_zc == 0
+    assert o.windows == 1
 
 
 def test_strerror(lib):
@@ -113,12 +114,14 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(tile_nt=100), "tile_nt"),
     (dict(tile_nt=512), "tile_nt"),
     (dict(tile_zc=10), "tile_zc"),
+    (dict(windows=0), "windows"),
+    (dict(windows=3), "(T/(windows*P))/dt_f"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
     args = dict(nx=64, nz=32, c_s=1.0, U=0.1, dt_f=0.2 / 64, dt_g=2.0 / 64,
                 P=8)
     opts = {k: kw.pop(k) for k in list(kw) if k in ("n_sound", "tile_nt",
-                                                   "tile_zc")}
+                                                   "tile_zc", "windows")}
     args.update(kw)
     rc, h = _create(lib, **args, **opts)
     assert rc == binding.PR_EINVAL and not h.value
