@@ -255,6 +255,7 @@ def main():
             speedup_batched_vs_plain=pms / ms,
             speedup_batched_vs_serial_fine=ser_ms / ms)
         del ser
+        res["windows"] = windows_leg(dev, max(1, args.steps // 2))
         if args.serve > 0:
             res["served"] = serve_leg(args.serve, args.serve_rate)
     if not args.no_cpu:
@@ -273,11 +274,68 @@ def main():
 
 
 def ctx_nf(prob):
-    return int(round(prob["T"] / prob["P"] / prob["dt_f"]))
+    return int(round(prob["T"] / (prob.get("windows", 1) * prob["P"]) /
+                     prob["dt_f"]))
 
 
 def ctx_ng(prob):
-    return int(round(prob["T"] / prob["P"] / prob["dt_g"]))
+    return int(round(prob["T"] / (prob.get("windows", 1) * prob["P"]) /
+                     prob["dt_g"]))
+
+
+def speedup_model(N_c, N_f, N_it, N_p, tau_c, tau_f, tau_qr):
+    """Eq. speedup of one parallel step: N_t tau_f over the coarse
+    prediction, N_it corrections and sweeps, and N_it subspace updates, with
+    N_t = N_c N_f fine steps per parallel step."""
+    N_t = N_c * N_f
+    return N_t * tau_f / (N_c * tau_c + N_it * (N_c * tau_c + N_t / N_p * tau_f)
+                          + N_it * tau_qr)
+
+
+def windows_leg(dev, steps):
+    """The paper's decomposition of the 512x256 run (Section 2.1): every
+    slice one coarse step, T / (P dt_g) windows of P slices in sequence."""
+    import torch
+    from paper_1510_02237_amd import binding, workloads as W
+    prob, K, u0 = W.config("c2w_512x256")
+    M, P = prob["windows"], prob["P"]
+    n_f, n_g = ctx_nf(prob), ctx_ng(prob)
+    u0_d = torch.from_numpy(u0).to(dev)
+    out = torch.empty_like(u0_d)
+    ctx = binding.Context.from_problem(prob, form="batched")
+    ctx.solve(u0_d, K, out=out)
+    ms, ms_fine, pts, st = timed_solves(ctx, u0_d, K, out, steps)
+    ref = ctx.serial_fine(u0_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.serial_fine(u0_d, out=ref)
+    torch.cuda.synchronize()
+    ser_ms = (time.perf_counter() - t0) * 1e3
+    refh = ref.cpu().numpy()
+    eps = _rel_l2(out.cpu().numpy(), refh)
+    eps0 = _rel_l2(ctx.solve(u0_d, 0).cpu().numpy(), refh)
+    # tau_c: one coarse step of one state (the coarse predictions, M P n_g
+    # dependent steps, device time); tau_f: one fine step of one state (the
+    # serial run); tau_QR: one subspace update.
+    tau_c = st["ms_coarse_init"] * 1e-3 / (M * P * n_g)
+    tau_f = ser_ms * 1e-3 / (M * P * n_f)
+    tau_qr = st["ms_update"] * 1e-3 / max(1, M * K)
+    # Concurrency the batched sweep reaches: slice-steps at the serial rate
+    # over the sweep time.
+    slice_steps = pts / (prob["nx"] * prob["nz"])
+    np_eff = slice_steps * tau_f / (ms_fine * 1e-3)
+    return dict(
+        workload="c2w_512x256", windows=M, P=P, K=K, n_f=n_f, n_g=n_g,
+        ms=ms, serial_fine_ms=ser_ms, speedup_vs_serial_fine=ser_ms / ms,
+        eps=eps, eps_coarse_only=eps0, phases_ms=dict(
+            coarse_init=st["ms_coarse_init"], fine=st["ms_fine"],
+            update=st["ms_update"], chain=st["ms_chain"]),
+        tau_c_us=tau_c * 1e6, tau_f_us=tau_f * 1e6,
+        tau_c_over_tau_f=tau_c / tau_f, tau_qr_ms=tau_qr * 1e3,
+        model_speedup_np_eq_p=speedup_model(P, n_f, K, P, tau_c, tau_f, tau_qr),
+        effective_np=np_eff,
+        model_speedup_effective_np=speedup_model(P, n_f, K, np_eff, tau_c,
+                                                 tau_f, tau_qr))
 
 
 def cpu_model():
