@@ -34,12 +34,21 @@ class Params:
 
     nx, nz      cells along x and z (dx = Lx/nx, dz = Lz/nz)
     c_s, U      sound speed and constant advection velocity along x
+    V           constant advection velocity along z (scheme "rk3" only; the
+                Section 3.2 runs advect along x)
     dt_f, dt_g  fine step (delta t) and coarse step (Delta t)
     P           number of time slices N_c of one window (parallel step)
     T           end time
     windows     number of parallel steps M_p (Section 2.1): [0, T] is
                 covered by ``windows`` windows of P slices each, a slice
                 being T / (windows * P) long
+    scheme      "split": the propagators of Section 3.2 (F: RK-3, fifth-order
+                upwind advection, fourth-order centred acoustics, damping;
+                G: partially split forward Euler).  "rk3": those of the
+                instability example of Section 3.1 (F: RK-3 with the
+                sixth-order centred advective flux; G: RK-3 with the
+                first-order upwind flux; both with second-order centred
+                acoustic fluxes and no damping)
     nu_f, nu_c  divergence-damping factors of F and G (eq. dampingCoeff)
     n_sound     acoustic substeps per coarse step (N_sound, Section 3.2)
     rank_tol    relative tolerance on |R_jj|/|R_11| for the rank of the
@@ -62,6 +71,14 @@ class Params:
     Lx: float = 1.0
     Lz: float = 1.0
     windows: int = 1
+    scheme: str = "split"
+    V: float = 0.0
+
+    def __post_init__(self):
+        if self.scheme not in ("split", "rk3"):
+            raise ValueError(f"unknown scheme {self.scheme!r}")
+        if self.scheme == "split" and self.V != 0.0:
+            raise ValueError("the split scheme advects along x only (V = 0)")
 
     @property
     def dx(self):
@@ -118,6 +135,14 @@ def flux_upwind5(q, vel, axis):
            - 5.0 * (_at(q, 2, axis) - _at(q, -1, axis))
            + 10.0 * (_at(q, 1, axis) - q))
     return vel / 60.0 * c6 - abs(vel) / 60.0 * dis
+
+
+def flux_centred6(q, axis):
+    """Sixth-order centred interface value of the Wicker-Skamarock family,
+    (37(q_i + q_{i+1}) - 8(q_{i-1} + q_{i+2}) + (q_{i-2} + q_{i+3}))/60."""
+    return (37.0 * (q + _at(q, 1, axis))
+            - 8.0 * (_at(q, -1, axis) + _at(q, 2, axis))
+            + (_at(q, -2, axis) + _at(q, 3, axis))) / 60.0
 
 
 def flux_upwind1(q, vel, axis):
@@ -185,6 +210,27 @@ def rhs_fine(q, prm: Params):
     fp = (-flux_div(flux_upwind5(p, U, X), dx, X)
           - c * (flux_div(flux_centred4(u, X), dx, X)
                  + flux_div(flux_centred4(w, Z), dz, Z)))
+    return np.stack([fu, fw, fp])
+
+
+def rhs_rk3_pair(q, prm: Params, coarse):
+    """f(q) of the Section 3.1 propagators (scheme "rk3"): advection with
+    velocity (U, V) by the sixth-order centred flux (F) or the first-order
+    upwind flux (G) in both directions, acoustic fluxes second-order
+    centred, no damping."""
+    X, Z = 1, 0
+    u, w, p = q
+    dx, dz, c, U, V = prm.dx, prm.dz, prm.c_s, prm.U, prm.V
+    if coarse:
+        adv = lambda f: (flux_div(flux_upwind1(f, U, X), dx, X)
+                         + flux_div(flux_upwind1(f, V, Z), dz, Z))
+    else:
+        adv = lambda f: (flux_div(U * flux_centred6(f, X), dx, X)
+                         + flux_div(V * flux_centred6(f, Z), dz, Z))
+    fu = -adv(u) - c * flux_div(flux_centred2(p, X), dx, X)
+    fw = -adv(w) - c * flux_div(flux_centred2(p, Z), dz, Z)
+    fp = -adv(p) - c * (flux_div(flux_centred2(u, X), dx, X)
+                        + flux_div(flux_centred2(w, Z), dz, Z))
     return np.stack([fu, fw, fp])
 
 

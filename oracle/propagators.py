@@ -9,22 +9,34 @@ G: partially split forward Euler: the advective (slow) tendency is computed
    once per coarse step and held fixed while N_sound forward-backward
    acoustic substeps advance the state.
 
-Both map a state over one slice of length T/P, i.e. n_f fine or n_g coarse
-steps, as F_{delta t}(q, t_{i+1}, t_i) and G_{Delta t}(q, t_{i+1}, t_i) of
-Section 2.1.  The system is autonomous, so neither depends on t_i.
+With scheme "rk3" (the instability example of Section 3.1) both F and G
+are RK3 with the right-hand sides of ``rhs_rk3_pair``: sixth-order centred
+advective fluxes in F, first-order upwind in G.
+
+Both map a state over one slice, i.e. n_f fine or n_g coarse steps, as
+F_{delta t}(q, t_{i+1}, t_i) and G_{Delta t}(q, t_{i+1}, t_i) of Section
+2.1.  The system is autonomous, so neither depends on t_i.
 """
 
 import numpy as np
 
-from .operators import Params, rhs_fine, coarse_slow_tendency, acoustic_substep
+from .operators import (Params, rhs_fine, rhs_rk3_pair, coarse_slow_tendency,
+                        acoustic_substep)
 
 
-def rk3_step(q, dt, prm: Params):
-    """One fine step: q* = q + dt/3 f(q), q** = q + dt/2 f(q*),
-    q^{n+1} = q + dt f(q**)."""
-    q1 = q + (dt / 3.0) * rhs_fine(q, prm)
-    q2 = q + (dt / 2.0) * rhs_fine(q1, prm)
-    return q + dt * rhs_fine(q2, prm)
+def _fine_rhs(prm: Params):
+    if prm.scheme == "rk3":
+        return lambda q, p: rhs_rk3_pair(q, p, coarse=False)
+    return rhs_fine
+
+
+def rk3_step(q, dt, prm: Params, rhs=None):
+    """One RK3 step of the fine right-hand side (or ``rhs``):
+    q* = q + dt/3 f(q), q** = q + dt/2 f(q*), q^{n+1} = q + dt f(q**)."""
+    f = _fine_rhs(prm) if rhs is None else rhs
+    q1 = q + (dt / 3.0) * f(q, prm)
+    q2 = q + (dt / 2.0) * f(q1, prm)
+    return q + dt * f(q2, prm)
 
 
 def fine_F(q, prm: Params, nsteps=None):
@@ -37,7 +49,12 @@ def fine_F(q, prm: Params, nsteps=None):
 
 
 def coarse_step(q, prm: Params):
-    """One partially split forward-Euler step of length dt_g."""
+    """One coarse step of length dt_g: partially split forward Euler, or
+    for scheme "rk3" one RK3 step of the first-order upwind right-hand
+    side."""
+    if prm.scheme == "rk3":
+        return rk3_step(q, prm.dt_g, prm,
+                        rhs=lambda x, p: rhs_rk3_pair(x, p, coarse=True))
     R = coarse_slow_tendency(q, prm)
     dtau = prm.dt_g / prm.n_sound
     for _ in range(prm.n_sound):

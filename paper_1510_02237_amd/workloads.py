@@ -110,6 +110,18 @@ def ic_fourier(nx, nz, seed, nmodes=32, kmax=64):
     return q
 
 
+def ic_cosine_bell(nx, nz, centre=(0.5, 0.5)):
+    """The initial value of the instability example (Section 3.1): u =
+    (cos(pi r) + 1)/2 with r = min(1, 4 sqrt(((x-x0)/0.5)^2 +
+    ((z-z0)/0.5)^2)), w = p = 0."""
+    X, Z = _cell_centres(nx, nz)
+    r = np.minimum(1.0, 4.0 * np.sqrt(((X - centre[0]) / 0.5) ** 2
+                                      + ((Z - centre[1]) / 0.5) ** 2))
+    q = np.zeros((3, nz, nx))
+    q[0] = 0.5 * (np.cos(np.pi * r) + 1.0)
+    return q
+
+
 # The five workloads: small oracle-scale run, single plain solve, batched
 # fused solve, serving stream, large single instance.
 CONFIGS = {
@@ -128,19 +140,37 @@ CONFIGS = {
     "c2w_512x256": dict(nx=512, nz=256, P=32, K=4, U=0.1, seed=2,
                         ic=dict(kind="bumps", nbumps=4, noise=1e-3),
                         windows="one_step"),
+    # The instability example of Section 3.1 on the acoustic-advection
+    # system: 40 x 40 cells, U = (1, 1), c_s = 1, RK-3 for both propagators
+    # (scheme "rk3"), 6 slices per window, 5 iterations.  Delta t = 1/66
+    # (coarse Courant number 0.606) and delta t = Delta t / 6 (0.101) make
+    # T = 1 exactly 11 windows of 6 coarse steps.
+    "demo_40x40": dict(nx=40, nz=40, P=6, K=5, U=1.0, V=1.0, c_s=1.0,
+                       ic=dict(kind="cosine_bell"), scheme="rk3",
+                       dt_g=1.0 / 66.0, coarse_ratio=6, windows=11),
 }
 
 
 def config(name):
     """(problem dict, K, initial state) of a named workload."""
     c = CONFIGS[name]
-    prob = problem(c["nx"], c["nz"], c["P"], U=c["U"])
+    prob = problem(c["nx"], c["nz"], c["P"], U=c["U"], c_s=c.get("c_s", 1.0),
+                   n_sound=1 if c.get("scheme") == "rk3" else None)
     if c.get("windows") == "one_step":
         prob["windows"] = one_coarse_step_windows(prob)
+    elif "windows" in c:
+        prob["windows"] = c["windows"]
+    if c.get("scheme") == "rk3":
+        # Section 3.1: no damping, no acoustic substeps
+        prob.update(scheme="rk3", V=c["V"], nu_f=0.0, nu_c=0.0, n_sound=1,
+                    dt_g=c["dt_g"], dt_f=c["dt_g"] / c["coarse_ratio"])
+        prob["T"] = prob["windows"] * prob["P"] * prob["dt_g"]
     ic = dict(c["ic"])
     kind = ic.pop("kind")
     if kind == "bumps":
         u0 = ic_bumps(c["nx"], c["nz"], c["seed"], **ic)
+    elif kind == "cosine_bell":
+        u0 = ic_cosine_bell(c["nx"], c["nz"], **ic)
     else:
         u0 = ic_fourier(c["nx"], c["nz"], c["seed"], **ic)
     return prob, c["K"], u0
