@@ -256,6 +256,7 @@ def main():
             speedup_batched_vs_serial_fine=ser_ms / ms)
         del ser
         res["windows"] = windows_leg(dev, max(1, args.steps // 2))
+        res["instability"] = instability_leg()
         if args.serve > 0:
             res["served"] = serve_leg(args.serve, args.serve_rate)
     if not args.no_cpu:
@@ -290,6 +291,42 @@ def speedup_model(N_c, N_f, N_it, N_p, tau_c, tau_f, tau_qr):
     N_t = N_c * N_f
     return N_t * tau_f / (N_c * tau_c + N_it * (N_c * tau_c + N_t / N_p * tau_f)
                           + N_it * tau_qr)
+
+
+def instability_leg():
+    """The instability example of Section 3.1 (workload demo_40x40): max|q|
+    after every window for the serial fine run, the original Parareal and
+    KSE-Parareal (the data of the paper's figure), computed by chaining
+    one-window solves, plus the time of each whole solve."""
+    import numpy as np
+    from paper_1510_02237_amd import binding, workloads as W
+    prob, K, u0 = W.config("demo_40x40")
+    M = prob["windows"]
+    one = dict(prob, windows=1, T=prob["T"] / M)
+    c1 = binding.Context.from_problem(one)
+    traj = {"fine": [], "parareal": [], "kse": []}
+    qf = qp = qk = u0
+    for _ in range(M):
+        qf = c1.serial_fine(qf)
+        qp = c1.solve(qp, K, parareal=True)
+        qk = c1.solve(qk, K)
+        traj["fine"].append(float(np.abs(qf).max()))
+        traj["parareal"].append(float(np.abs(qp).max()))
+        traj["kse"].append(float(np.abs(qk).max()))
+    ctx = binding.Context.from_problem(prob)
+    times = {}
+    for name, kw in (("kse", {}), ("parareal", {"parareal": True})):
+        ctx.solve(u0, K, **kw)
+        t0 = time.perf_counter()
+        ctx.solve(u0, K, **kw)
+        times[name] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    ref = ctx.serial_fine(u0)
+    times["serial_fine"] = (time.perf_counter() - t0) * 1e3
+    return dict(workload="demo_40x40", windows=M, P=prob["P"], K=K,
+                U=prob["U"], V=prob["V"], c_s=prob["c_s"],
+                max_abs_q_per_window=traj, ms=times,
+                eps_kse=_rel_l2(qk, ref), eps_parareal=_rel_l2(qp, ref))
 
 
 def windows_leg(dev, steps):

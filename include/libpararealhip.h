@@ -75,6 +75,21 @@ enum { PR_MEM_HOST = 0, PR_MEM_DEVICE = 1 };
  * results equal to rounding for the stagewise form. */
 enum { PR_FORM_BATCHED = 0, PR_FORM_PLAIN = 1, PR_FORM_STAGEWISE = 2 };
 
+/* Which pair of propagators.
+ *   PR_SCHEME_SPLIT (default): those of Section 3.2.  F is RK-3 with
+ *     fifth-order upwind advection, fourth-order centred acoustics and
+ *     divergence damping (nu_f).  G is partially split forward Euler with
+ *     N_sound forward-backward acoustic substeps and damping (nu_c).
+ *     Advection is along x (U).
+ *   PR_SCHEME_RK3: those of the instability example of Section 3.1.  F is
+ *     RK-3 with the sixth-order centred advective flux; G is RK-3 with the
+ *     first-order upwind flux (step dt_g).  Both use second-order centred
+ *     acoustic fluxes and no damping (nu_f, nu_c and n_sound are unused).
+ *     Advection is along x and z with velocity (U, pr_opts.V).  Every sweep
+ *     runs the unfused stage kernels (the form is ignored); the server does
+ *     not accept this scheme. */
+enum { PR_SCHEME_SPLIT = 0, PR_SCHEME_RK3 = 1 };
+
 typedef struct pr_grid {
   int32_t nx, nz;   /* cells along x and z, each >= 8                  */
   double Lx, Lz;    /* domain lengths (> 0)                            */
@@ -108,6 +123,9 @@ typedef struct pr_opts {
                              dt_g = T / (windows * P) every slice is one
                              coarse step, as in the paper's runs.  The server
                              accepts only 1.                                   */
+  int32_t scheme;         /* PR_SCHEME_SPLIT (default) or PR_SCHEME_RK3       */
+  double V;               /* advection velocity along z; must be 0 with
+                             PR_SCHEME_SPLIT (default 0)                       */
 } pr_opts;
 
 typedef struct pr_ctx pr_ctx;

@@ -43,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("n_sound", ctypes.c_int32), ("rank_tol", ctypes.c_double),
                 ("form", ctypes.c_int32), ("skip_converged", ctypes.c_int32),
                 ("tile_nt", ctypes.c_int32), ("tile_zc", ctypes.c_int32),
-                ("windows", ctypes.c_int32)]
+                ("windows", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("V", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -131,12 +132,17 @@ def _err(code, ctx=None):
     return PRError(code, msg or lib.pr_strerror(code).decode())
 
 
+SCHEMES = {"split": 0, "rk3": 1}
+
+
 def default_opts(**kw):
     o = Opts()
     load().pr_opts_default(ctypes.byref(o))
     for k, v in kw.items():
         if k == "form" and isinstance(v, str):
             v = FORMS[v]
+        if k == "scheme" and isinstance(v, str):
+            v = SCHEMES[v]
         setattr(o, k, v)
     return o
 
@@ -223,7 +229,8 @@ class Context:
         """From a workload dict (paper_1510_02237_amd.workloads.problem)."""
         o = dict(nu_f=prob["nu_f"], nu_c=prob["nu_c"],
                  n_sound=prob["n_sound"], rank_tol=prob["rank_tol"],
-                 windows=prob.get("windows", 1))
+                 windows=prob.get("windows", 1),
+                 scheme=prob.get("scheme", "split"), V=prob.get("V", 0.0))
         o.update(opts)
         return cls(prob["nx"], prob["nz"], prob["c_s"], prob["U"],
                    prob["dt_f"], prob["dt_g"], prob["P"], T=prob["T"], **o)

@@ -22,6 +22,8 @@ struct pr_ctx {
   int64_t ld = 0;  // padded state stride of internal buffers (multiple of 64)
   prh::FineCoef fc{};
   prh::CoarseCoef cc{};
+  prh::Rk3Coef rf{}, rg{};  // scheme PR_SCHEME_RK3: fine and coarse weights
+  bool rk3 = false;
   int sgn = 1;
   std::vector<int> coarse_chunks;  // substeps per launch within a coarse step
 
@@ -45,7 +47,8 @@ struct pr_ctx {
   double* X = nullptr;    // wcap: new raw columns (projected in place)
   double* DX = nullptr;   // wcap: their F - G images
   double* Yb = nullptr;   // wcap: CholQR intermediate, batched-G pong
-  double* Rb = nullptr;   // wcap: frozen slow tendency when N_sound > 4
+  double* Rb = nullptr;   // wcap: frozen slow tendency when N_sound > 4, or
+                          // the step buffer of the RK-3 coarse propagator
   double* st = nullptr;   // kSingle single states
   double* S = nullptr;    // rcap basis vectors
   double* D = nullptr;    // rcap vectors F(s_j) - G(s_j)

@@ -83,6 +83,27 @@ hipError_t launch_fine_stage(const double* in, int64_t in_stride,
                              int sgn, hipStream_t s);
 
 // ---------------------------------------------------------------------------
+// The propagator pair of the instability example (Section 3.1, scheme
+// PR_SCHEME_RK3): RK-3 stages of
+//   f(q)_field = sum_{m=-3..3} (wx[m+3] q(i+m, j) + wz[m+3] q(i, j+m))
+//              - acoustic centred differences,
+// with the advective weights of the sixth-order centred flux (F) or the
+// first-order upwind flux (G), advection velocity included.
+// ---------------------------------------------------------------------------
+struct Rk3Coef {
+  double wx[7], wz[7];   // advective weights at offsets -3..3
+  double cx2, cz2;       // c_s/(2 dx), c_s/(2 dz)
+};
+
+// out = base + beta * f(in) over ns states (each array with its own state
+// stride), one point per thread, neighbours read from global memory.
+hipError_t launch_rk3_stage(const double* in, int64_t in_stride,
+                            const double* base, int64_t base_stride,
+                            double* out, int64_t out_stride, int nx, int nz,
+                            int nstates, const Rk3Coef& c, double beta,
+                            hipStream_t s);
+
+// ---------------------------------------------------------------------------
 // Coarse propagator (Section 3.2: partially split forward Euler; the slow
 // advective tendency -U * (first-order upwind derivative) is frozen over
 // N_sound forward-backward acoustic substeps with divergence damping

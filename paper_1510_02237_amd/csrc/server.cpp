@@ -508,6 +508,8 @@ extern "C" int pr_submit_ex(pr_server* s, const pr_grid* g, double c_s,
   if (K < 0) return set_serr(s, PR_EINVAL, "K must be >= 0");
   if (o->windows != 1)
     return set_serr(s, PR_EINVAL, "the server solves one window (windows = 1)");
+  if (o->scheme != PR_SCHEME_SPLIT)
+    return set_serr(s, PR_EINVAL, "the server runs the split scheme only");
   int nf, ng;
   std::string msg;
   int rc = pr_validate(g, c_s, U, dt_f, dt_g, P, o, &nf, &ng, &msg);

@@ -120,6 +120,11 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
     return fail("tile_zc must be a multiple of 4 in [0, 4096]");
   if (o->windows < 1 || o->windows > (1 << 20))
     return fail("windows must be in [1, 2^20]");
+  if (o->scheme != PR_SCHEME_SPLIT && o->scheme != PR_SCHEME_RK3)
+    return fail("scheme must be PR_SCHEME_SPLIT or PR_SCHEME_RK3");
+  if (!std::isfinite(o->V)) return fail("V must be finite");
+  if (o->scheme == PR_SCHEME_SPLIT && o->V != 0.0)
+    return fail("V must be 0 with PR_SCHEME_SPLIT (advection along x)");
   const double slice = g->T / ((double)o->windows * P);
   if (int_ratio(slice, dt_f, nf)) {
     snprintf(buf, sizeof buf, "(T/(windows*P))/dt_f = %.17g is not an integer",
@@ -169,6 +174,36 @@ static void make_coef(pr_ctx* c) {
   const int nch = (ns + kCoarseMaxSubPerLaunch - 1) / kCoarseMaxSubPerLaunch;
   c->coarse_chunks.assign(nch, ns / nch);
   for (int q = 0; q < ns % nch; ++q) c->coarse_chunks[q] += 1;
+  // Section 3.1 pair.  F: sixth-order centred flux differenced, point
+  // weights (-1, 9, -45, 0, 45, -9, 1)/(60 h) at offsets -3..3; G:
+  // first-order upwind, U (q_i - q_{i-1})/h for U >= 0, U (q_{i+1} - q_i)/h
+  // for U < 0.  Stored as weights of f = -advection.
+  c->rk3 = c->o.scheme == PR_SCHEME_RK3;
+  if (c->rk3) {
+    static const double c6[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
+    const double V = c->o.V;
+    for (int k = 0; k < 7; ++k) {
+      c->rf.wx[k] = -U * c6[k] / (60.0 * dx);
+      c->rf.wz[k] = -V * c6[k] / (60.0 * dz);
+      c->rg.wx[k] = c->rg.wz[k] = 0.0;
+    }
+    if (U >= 0) {
+      c->rg.wx[3] = -U / dx;
+      c->rg.wx[2] = U / dx;
+    } else {
+      c->rg.wx[4] = -U / dx;
+      c->rg.wx[3] = U / dx;
+    }
+    if (V >= 0) {
+      c->rg.wz[3] = -V / dz;
+      c->rg.wz[2] = V / dz;
+    } else {
+      c->rg.wz[4] = -V / dz;
+      c->rg.wz[3] = V / dz;
+    }
+    c->rf.cx2 = c->rg.cx2 = cs / (2.0 * dx);
+    c->rf.cz2 = c->rg.cz2 = cs / (2.0 * dz);
+  }
 }
 
 static void clear_graphs(pr_ctx* c) {
@@ -215,7 +250,10 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
     RC(dalloc(c, &c->X, w, "work"));
     RC(dalloc(c, &c->DX, w, "work"));
     RC(dalloc(c, &c->Yb, w, "work"));
-    if (c->coarse_chunks.size() > 1) RC(dalloc(c, &c->Rb, w, "work"));
+    // third scratch block of run_coarse: the stored slow tendency (split
+    // scheme with more than one substep chunk) or an RK-3 step (rk3)
+    if (c->coarse_chunks.size() > 1 || c->rk3)
+      RC(dalloc(c, &c->Rb, w, "work"));
     c->wcap = wcap;
     changed = true;
   }
@@ -295,7 +333,7 @@ int prh::retarget(pr_ctx* c, double c_s, double U, double dt_f, double dt_g,
   make_coef(c);
   clear_graphs(c);
   c->r = 0;
-  if (c->coarse_chunks.size() > 1 && !c->Rb && c->wcap > 0)
+  if ((c->coarse_chunks.size() > 1 || c->rk3) && !c->Rb && c->wcap > 0)
     RC(dalloc(c, &c->Rb, (size_t)c->wcap * c->ld, "work"));
   return PR_OK;
 }
@@ -361,7 +399,7 @@ static void tile_for(pr_ctx* c, int ns, int* nt, int* zc) {
 // every candidate on the context's own buffers (Q -> Qt); the choice only
 // changes the speed, never the result.
 int prh::autotune(pr_ctx* c, int ns) {
-  if (c->o.tile_nt && c->o.tile_zc) return PR_OK;
+  if (c->rk3 || (c->o.tile_nt && c->o.tile_zc)) return PR_OK;
   {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     if (g_tiles.count(TileKey{c->g.nx, c->g.nz, ns, c->sgn})) return PR_OK;
@@ -448,12 +486,21 @@ int prh::run_sweep(pr_ctx* c, const double* in, int64_t is, double* out,
       double* dst = to_out ? out : ping;
       const int64_t dst_s = to_out ? os : ps;
       const double dt = c->fc.dt;
-      HC(launch_fine_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns,
-                           c->fc, dt / 3.0, c->sgn, c->stream));
-      HC(launch_fine_stage(A, ps, src, sst, B, ps, c->g.nx, c->g.nz, ns, c->fc,
-                           0.5 * dt, c->sgn, c->stream));
-      HC(launch_fine_stage(B, ps, src, sst, dst, dst_s, c->g.nx, c->g.nz, ns,
-                           c->fc, dt, c->sgn, c->stream));
+      if (c->rk3) {
+        HC(launch_rk3_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns,
+                            c->rf, dt / 3.0, c->stream));
+        HC(launch_rk3_stage(A, ps, src, sst, B, ps, c->g.nx, c->g.nz, ns,
+                            c->rf, 0.5 * dt, c->stream));
+        HC(launch_rk3_stage(B, ps, src, sst, dst, dst_s, c->g.nx, c->g.nz, ns,
+                            c->rf, dt, c->stream));
+      } else {
+        HC(launch_fine_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns,
+                             c->fc, dt / 3.0, c->sgn, c->stream));
+        HC(launch_fine_stage(A, ps, src, sst, B, ps, c->g.nx, c->g.nz, ns,
+                             c->fc, 0.5 * dt, c->sgn, c->stream));
+        HC(launch_fine_stage(B, ps, src, sst, dst, dst_s, c->g.nx, c->g.nz, ns,
+                             c->fc, dt, c->sgn, c->stream));
+      }
       src = dst;
       sst = dst_s;
     }
@@ -486,6 +533,24 @@ int prh::run_sweep(pr_ctx* c, const double* in, int64_t is, double* out,
 int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
                     int64_t stride, double* pa, double* pb, double* R) {
   if (ns <= 0) return PR_OK;
+  if (c->rk3) {
+    // n_g RK-3 steps of the upwind right-hand side: stages in pa and pb,
+    // steps alternating between out and R so that the last one lands in
+    // out and no stage writes its own input.
+    const double dt = c->dt_g;
+    const double* src = in;
+    for (int st = 0; st < c->n_g; ++st) {
+      double* dst = ((c->n_g - 1 - st) % 2 == 0) ? out : R;
+      HC(launch_rk3_stage(src, stride, src, stride, pa, stride, c->g.nx,
+                          c->g.nz, ns, c->rg, dt / 3.0, c->stream));
+      HC(launch_rk3_stage(pa, stride, src, stride, pb, stride, c->g.nx,
+                          c->g.nz, ns, c->rg, 0.5 * dt, c->stream));
+      HC(launch_rk3_stage(pb, stride, src, stride, dst, stride, c->g.nx,
+                          c->g.nz, ns, c->rg, dt, c->stream));
+      src = dst;
+    }
+    return PR_OK;
+  }
   const int nch = (int)c->coarse_chunks.size();
   const int total = c->n_g * nch;
   const double* src = in;
@@ -898,6 +963,7 @@ extern "C" int pr_create_ex(const pr_grid* g, double c_s, double U,
   c->d = 3 * c->n;
   c->ld = (c->d + 63) / 64 * 64;
   make_coef(c);
+  if (c->rk3) c->o.form = PR_FORM_STAGEWISE;  // only stage kernels
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
     if (hip_stream) {
@@ -949,7 +1015,8 @@ extern "C" int pr_set_form(pr_ctx* c, int32_t form) {
   if (!c) return PR_EINVAL;
   if (form < 0 || form > PR_FORM_STAGEWISE)
     return set_error(c, PR_EINVAL, "unknown form %d", form);
-  c->o.form = form;
+  // The Section 3.1 pair has only the stage kernels.
+  c->o.form = c->rk3 ? PR_FORM_STAGEWISE : form;
   return PR_OK;
 }
 

@@ -129,12 +129,87 @@ double spectral_radius(M3 H) {
   return r;
 }
 
+// R(Z) = I + Z + Z^2/2 + Z^3/6 of Z = dt A.
+M3 rk3_amplification(M3 Z, double dt) {
+  for (auto& row : Z.a)
+    for (auto& v : row) v *= dt;
+  const M3 Z2 = mul(Z, Z), Z3 = mul(Z2, Z);
+  M3 R;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      R.a[i][j] = (i == j ? 1.0 : 0.0) + Z.a[i][j] + 0.5 * Z2.a[i][j] +
+                  Z3.a[i][j] / 6.0;
+  return R;
+}
+
+// Symbol matrix of the Section 3.1 right-hand side: scalar advection
+// symbol adv on the diagonal, centred second-order acoustics.
+M3 acoustic2(cd adv, cd dx2, cd dz2, double c_s) {
+  M3 Z;
+  Z.a[0][0] = adv;
+  Z.a[0][1] = 0.0;
+  Z.a[0][2] = -c_s * dx2;
+  Z.a[1][0] = 0.0;
+  Z.a[1][1] = adv;
+  Z.a[1][2] = -c_s * dz2;
+  Z.a[2][0] = -c_s * dx2;
+  Z.a[2][1] = -c_s * dz2;
+  Z.a[2][2] = adv;
+  return Z;
+}
+
+}  // namespace
+
+namespace {
+
+// Scan for the pair of the instability example (Section 3.1): F and G are
+// both RK-3, with the sixth-order centred and the first-order upwind
+// advective symbols along x (U) and z (V).
+void scan_rk3(int nx, int nz, double dx, double dz, double c_s, double U,
+              double V, double dt_f, double dt_g, int kxn, int kzn,
+              double* rho_f, double* rho_g) {
+  const cd I(0.0, 1.0);
+  const double two_pi = 2.0 * M_PI;
+  auto c6 = [&](double t, double h) {
+    return I * (45.0 * std::sin(t) - 9.0 * std::sin(2.0 * t) +
+                std::sin(3.0 * t)) / (30.0 * h);
+  };
+  auto up1 = [&](double t, double h, double vel) {
+    return vel >= 0 ? (1.0 - std::exp(-I * t)) / h : (std::exp(I * t) - 1.0) / h;
+  };
+  double rf = 0.0, rg = 0.0;
+  for (int a = 0; a < kxn; ++a) {
+    const long long kx = kxn == nx ? a : (long long)a * nx / 256;
+    const double tx = two_pi * (double)kx / nx;
+    for (int b = 0; b < kzn; ++b) {
+      const long long kz = kzn == nz ? b : (long long)b * nz / 256;
+      const double tz = two_pi * (double)kz / nz;
+      const cd dx2 = I * std::sin(tx) / dx, dz2 = I * std::sin(tz) / dz;
+      const cd af = -U * c6(tx, dx) - V * c6(tz, dz);
+      const cd ag = -U * up1(tx, dx, U) - V * up1(tz, dz, V);
+      rf = std::max(rf, spectral_radius(
+                            rk3_amplification(acoustic2(af, dx2, dz2, c_s), dt_f)));
+      rg = std::max(rg, spectral_radius(
+                            rk3_amplification(acoustic2(ag, dx2, dz2, c_s), dt_g)));
+    }
+  }
+  *rho_f = rf;
+  *rho_g = rg;
+}
+
 }  // namespace
 
 int pr_check_stability_impl(const pr_grid* g, double c_s, double U,
                             double dt_f, double dt_g, const pr_opts* o,
                             double* rho_f, double* rho_g) {
   const int nx = g->nx, nz = g->nz;
+  if (o->scheme == PR_SCHEME_RK3) {
+    const bool all = (long long)nx * nz <= 65536;
+    scan_rk3(nx, nz, g->Lx / nx, g->Lz / nz, c_s, U, o->V, dt_f, dt_g,
+             all || nx <= 256 ? nx : 256, all || nz <= 256 ? nz : 256, rho_f,
+             rho_g);
+    return PR_OK;
+  }
   const double dx = g->Lx / nx, dz = g->Lz / nz;
   const double ax_f = o->nu_f * dx * dx / dt_f, az_f = o->nu_f * dz * dz / dt_f;
   const double dtau = dt_g / o->n_sound;

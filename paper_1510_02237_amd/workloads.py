@@ -142,12 +142,14 @@ CONFIGS = {
                         windows="one_step"),
     # The instability example of Section 3.1 on the acoustic-advection
     # system: 40 x 40 cells, U = (1, 1), c_s = 1, RK-3 for both propagators
-    # (scheme "rk3"), 6 slices per window, 5 iterations.  Delta t = 1/66
-    # (coarse Courant number 0.606) and delta t = Delta t / 6 (0.101) make
-    # T = 1 exactly 11 windows of 6 coarse steps.
+    # (scheme "rk3"), 6 slices per window, 5 iterations.  Delta t = 1/72
+    # (Courant number U Delta t / dx = 0.556 per direction) and delta t =
+    # Delta t / 6 (0.093) make T = 1 exactly 12 windows of 6 coarse steps;
+    # Delta t = 1/66 (0.606) would make the coarse propagator itself
+    # unstable at c_s = 1.
     "demo_40x40": dict(nx=40, nz=40, P=6, K=5, U=1.0, V=1.0, c_s=1.0,
                        ic=dict(kind="cosine_bell"), scheme="rk3",
-                       dt_g=1.0 / 66.0, coarse_ratio=6, windows=11),
+                       dt_g=1.0 / 72.0, coarse_ratio=6, windows=12),
 }
 
 

@@ -96,6 +96,38 @@ def test_stability_of_workload_rule(lib):
     assert rg > 1.05
 
 
+@pytest.mark.parametrize("U,V,c_s", [(1.0, 1.0, 1.0), (-0.7, 0.4, 0.0),
+                                     (0.3, -1.2, 2.0)])
+def test_stability_scan_rk3_scheme(lib, U, V, c_s):
+    """Section 3.1 pair: the scan's spectral radii against numpy eigenvalues
+    of R(dt A) with A written from the stencil weights (the symbols the
+    oracle's tests pin)."""
+    from test_oracle_rk3_scheme import rk3_symbol
+    nx = nz = 16
+    dt_g = 0.6 / nx / (abs(U) + abs(V) + c_s)
+    dt_f = dt_g / 6
+    prm = Params(nx=nx, nz=nz, c_s=c_s, U=U, V=V, dt_f=dt_f, dt_g=dt_g, P=1,
+                 T=dt_g, nu_f=0.0, nu_c=0.0, n_sound=1, scheme="rk3")
+    want_f = want_g = 0.0
+    for kx in range(nx):
+        for kz in range(nz):
+            want_f = max(want_f, np.abs(np.linalg.eigvals(
+                rk3_poly(dt_f * rk3_symbol(prm, kx, kz, False)))).max())
+            want_g = max(want_g, np.abs(np.linalg.eigvals(
+                rk3_poly(dt_g * rk3_symbol(prm, kx, kz, True)))).max())
+    got_f, got_g = binding.check_stability(nx, nz, c_s, U, dt_f, dt_g,
+                                           scheme="rk3", V=V, n_sound=1)
+    assert abs(got_f - want_f) < 1e-12 and abs(got_g - want_g) < 1e-12
+
+
+def test_demo_pair_is_stable(lib):
+    prob, K, u0 = W.config("demo_40x40")
+    rf, rg = binding.check_stability(40, 40, prob["c_s"], prob["U"],
+                                     prob["dt_f"], prob["dt_g"], scheme="rk3",
+                                     V=prob["V"], n_sound=1)
+    assert rf <= 1 + 1e-12 and rg <= 1 + 1e-12
+
+
 def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     h = ctypes.c_void_p()
     o = binding.default_opts(**opts)
@@ -116,12 +148,15 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(tile_zc=10), "tile_zc"),
     (dict(windows=0), "windows"),
     (dict(windows=3), "(T/(windows*P))/dt_f"),
+    (dict(scheme=7), "scheme"),
+    (dict(V=0.1), "V must be 0"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
     args = dict(nx=64, nz=32, c_s=1.0, U=0.1, dt_f=0.2 / 64, dt_g=2.0 / 64,
                 P=8)
     opts = {k: kw.pop(k) for k in list(kw) if k in ("n_sound", "tile_nt",
-                                                   "tile_zc", "windows")}
+                                                   "tile_zc", "windows",
+                                                   "scheme", "V")}
     args.update(kw)
     rc, h = _create(lib, **args, **opts)
     assert rc == binding.PR_EINVAL and not h.value

@@ -114,9 +114,9 @@ def test_demo_workload_parameters():
     prob, K, u0 = W.config("demo_40x40")
     prm = Params(**prob)
     assert prm.scheme == "rk3" and (prm.U, prm.V, prm.c_s) == (1.0, 1.0, 1.0)
-    assert prm.n_g == 1 and prm.n_f == 6 and prm.windows * prm.P == 66
+    assert prm.n_g == 1 and prm.n_f == 6 and prm.windows * prm.P == 72
     assert prm.T == pytest.approx(1.0)
-    assert prm.dt_g * prm.U / prm.dx == pytest.approx(40 / 66)
+    assert prm.dt_g * prm.U / prm.dx == pytest.approx(40 / 72)
     assert u0[0].max() <= 1.0 and u0[0].min() == 0.0 and not u0[1:].any()
 
 
@@ -127,8 +127,8 @@ def test_original_parareal_unstable_kse_stable(c_s):
     the fine solution (c_s = 0 is the pure-advection case of the paper's
     first figure, with u advected and w = p = 0)."""
     prob, K, u0 = W.config("demo_40x40")
-    prob = dict(prob, c_s=c_s, windows=5)
-    prob["T"] = 5 * prob["P"] * prob["dt_g"]
+    prob = dict(prob, c_s=c_s, windows=7)
+    prob["T"] = 7 * prob["P"] * prob["dt_g"]
     prm = Params(**prob)
     par = oracle.kse_parareal(u0, prm, K=K, krylov=False)
     kse = oracle.kse_parareal(u0, prm, K=K)
@@ -144,4 +144,4 @@ def test_original_parareal_unstable_kse_stable(c_s):
     # ... while the original Parareal grows without bound.
     amax = [np.abs(e).max() for e in par["window_ends"]]
     assert amax[-1] > 100 * fmax
-    assert all(b > 5 * a for a, b in zip(amax[2:], amax[3:]))
+    assert amax[-1] > 5 * amax[-2] > 25 * amax[-3]
