@@ -126,6 +126,15 @@ typedef struct pr_opts {
   int32_t scheme;         /* PR_SCHEME_SPLIT (default) or PR_SCHEME_RK3       */
   double V;               /* advection velocity along z; must be 0 with
                              PR_SCHEME_SPLIT (default 0)                       */
+  double stop_tol;        /* stopping criterion of Section 2.1: 0 (default)
+                             runs exactly K iterations; > 0 ends a window
+                             after the first iteration k whose error
+                             estimate r^k = max_i ||q^{k+1}_i - q^k_i|| /
+                             max_i ||q^{k+1}_i|| (Euclidean norms of whole
+                             states, i = 1..P) is <= stop_tol, K being the
+                             maximum.  Costs one copy and two norm passes
+                             over the iterates per iteration.  The server
+                             accepts only 0.                                   */
 } pr_opts;
 
 typedef struct pr_ctx pr_ctx;
@@ -139,6 +148,8 @@ typedef struct pr_stats {
   int32_t iterations;
   int32_t rank[64];         /* dim S^k after iteration k (k < 64)         */
   int64_t fine_point_steps; /* grid points x RK-3 steps done by the sweeps */
+  double residual[64];      /* r^k after iteration k (k < 64) when
+                               stop_tol > 0, else 0                        */
 } pr_stats;
 
 /* Fills the defaults listed above. */

@@ -79,9 +79,25 @@ def _vec(states):
                     axis=1)
 
 
-def kse_parareal(u0, prm: Params, K, krylov=True, history=False):
+def residual(new, old):
+    """The error estimate of Section 2.1, r^k = max_i ||q^{k+1}_i - q^k_i||
+    (Euclidean norm over all fields, i = 1..N_c), divided by
+    max_i ||q^{k+1}_i|| so that it does not depend on the scale of u0."""
+    num = max(np.linalg.norm(np.ravel(a) - np.ravel(b))
+              for a, b in zip(new[1:], old[1:]))
+    den = max(np.linalg.norm(np.ravel(a)) for a in new[1:])
+    return float(num / den) if den > 0 else 0.0
+
+
+def kse_parareal(u0, prm: Params, K, krylov=True, history=False,
+                 stop_tol=0.0):
     """Algorithm 2 (or Algorithm 1 with ``krylov=False``, i.e. S = empty)
     over the ``prm.windows`` parallel steps of Section 2.1.
+
+    With ``stop_tol`` > 0 a window stops after the first iteration k whose
+    error estimate ``residual`` is <= stop_tol (Section 2.1's stopping
+    criterion), K being the maximum; ``residuals`` and ``iterations`` of the
+    last window are returned.
 
     Returns the last window's dict (see ``_one_window``) with, in addition,
       window_ends   the final state q^K_P of every window
@@ -93,7 +109,8 @@ def kse_parareal(u0, prm: Params, K, krylov=True, history=False):
     ends, wranks = [], []
     out = None
     for _ in range(prm.windows):
-        out = _one_window(u, prm, K, krylov=krylov, history=history)
+        out = _one_window(u, prm, K, krylov=krylov, history=history,
+                          stop_tol=stop_tol)
         u = out["q"][prm.P]
         ends.append(u)
         if krylov:
@@ -104,7 +121,8 @@ def kse_parareal(u0, prm: Params, K, krylov=True, history=False):
     return out
 
 
-def _one_window(u0, prm: Params, K, krylov=True, history=False):
+def _one_window(u0, prm: Params, K, krylov=True, history=False,
+                stop_tol=0.0):
     """One parallel step of Algorithm 2 (Algorithm 1 with ``krylov=False``)
     on the P slices that start at u0.
 
@@ -115,6 +133,8 @@ def _one_window(u0, prm: Params, K, krylov=True, history=False):
       S, FS   the last basis and its fine images (krylov only)
       qt      the last iteration's fine results, qt[i+1] = F(q^{K-1}_i)
       iters   with history=True: q^k for k = 0..K
+      residuals  r^k of every iteration done (see ``residual``)
+      iterations the number of iterations done
     """
     u0 = np.asarray(u0, dtype=np.float64)
     P = prm.P
@@ -129,6 +149,7 @@ def _one_window(u0, prm: Params, K, krylov=True, history=False):
     FS = np.zeros((d, 0))
     ranks, diags, iters = [], [], [list(q)] if history else None
     qt = None
+    residuals = []
     for k in range(K):
         # Parallel predictor step.
         qt = [None] + [fine_F(q[i], prm) for i in range(P)]
@@ -146,10 +167,14 @@ def _one_window(u0, prm: Params, K, krylov=True, history=False):
             k_new = kse_apply(new[i], S, FS, prm)
             k_old = kse_apply(q[i], S, FS, prm)
             new.append(qt[i + 1] + (k_new - k_old))
+        residuals.append(residual(new, q))
         q = new
         if history:
             iters.append(list(q))
-    out = {"q": q, "qt": qt}
+        if stop_tol > 0 and residuals[-1] <= stop_tol:
+            break
+    out = {"q": q, "qt": qt, "residuals": residuals,
+           "iterations": len(residuals)}
     if krylov:
         out.update(ranks=ranks, diagR=diags, S=S, FS=FS)
     if history:

@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
                 ("form", ctypes.c_int32), ("skip_converged", ctypes.c_int32),
                 ("tile_nt", ctypes.c_int32), ("tile_zc", ctypes.c_int32),
                 ("windows", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("V", ctypes.c_double)]
+                ("V", ctypes.c_double), ("stop_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -54,7 +54,8 @@ class Stats(ctypes.Structure):
                 ("ms_chain", ctypes.c_double),
                 ("iterations", ctypes.c_int32),
                 ("rank", ctypes.c_int32 * 64),
-                ("fine_point_steps", ctypes.c_int64)]
+                ("fine_point_steps", ctypes.c_int64),
+                ("residual", ctypes.c_double * 64)]
 
 
 _lib = None
@@ -315,4 +316,5 @@ class Context:
                     ms_fine=s.ms_fine, ms_update=s.ms_update,
                     ms_chain=s.ms_chain, iterations=s.iterations,
                     rank=list(s.rank[:s.iterations]),
-                    fine_point_steps=s.fine_point_steps)
+                    fine_point_steps=s.fine_point_steps,
+                    residual=list(s.residual[:s.iterations]))

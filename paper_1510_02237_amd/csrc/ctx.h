@@ -55,6 +55,8 @@ struct pr_ctx {
   double* small = nullptr;
   int* ism = nullptr;     // device ints: rank1, rank2, finite flag
   int* h_ism = nullptr;   // pinned host mirror
+  double* nrm = nullptr;    // stopping criterion: 2 (P + 1) squared norms
+  double* h_nrm = nullptr;  // pinned host mirror
   size_t small_len = 0;
   int r = 0;              // current basis dimension
   double* d_r11sq = nullptr;

@@ -510,6 +510,8 @@ extern "C" int pr_submit_ex(pr_server* s, const pr_grid* g, double c_s,
     return set_serr(s, PR_EINVAL, "the server solves one window (windows = 1)");
   if (o->scheme != PR_SCHEME_SPLIT)
     return set_serr(s, PR_EINVAL, "the server runs the split scheme only");
+  if (o->stop_tol != 0.0)
+    return set_serr(s, PR_EINVAL, "the server runs a fixed K (stop_tol = 0)");
   int nf, ng;
   std::string msg;
   int rc = pr_validate(g, c_s, U, dt_f, dt_g, P, o, &nf, &ng, &msg);

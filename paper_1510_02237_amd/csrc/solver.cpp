@@ -125,6 +125,8 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
   if (!std::isfinite(o->V)) return fail("V must be finite");
   if (o->scheme == PR_SCHEME_SPLIT && o->V != 0.0)
     return fail("V must be 0 with PR_SCHEME_SPLIT (advection along x)");
+  if (!(o->stop_tol >= 0) || !std::isfinite(o->stop_tol))
+    return fail("stop_tol must be finite and >= 0");
   const double slice = g->T / ((double)o->windows * P);
   if (int_ratio(slice, dt_f, nf)) {
     snprintf(buf, sizeof buf, "(T/(windows*P))/dt_f = %.17g is not an integer",
@@ -242,6 +244,9 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
     RC(dalloc(c, &c->st, (size_t)kSingle * ld, "single states"));
     HC(hipMalloc((void**)&c->ism, 16 * sizeof(int)));
     HC(hipHostMalloc((void**)&c->h_ism, 16 * sizeof(int), hipHostMallocDefault));
+    HC(hipMalloc((void**)&c->nrm, 2 * (size_t)(c->P + 1) * sizeof(double)));
+    HC(hipHostMalloc((void**)&c->h_nrm, 2 * (size_t)(c->P + 1) * sizeof(double),
+                     hipHostMallocDefault));
     changed = true;
   }
   if (wcap > c->wcap) {
@@ -781,7 +786,7 @@ static int copy_state_out(pr_ctx* c, double* dst, const double* src, int mem) {
 static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
                         double* U_K, double* slices, int mem, bool krylov) {
   const int P = c->P;
-  const int Keff = std::min<int>(K, P);
+  int Keff = std::min<int>(K, P);  // lowered by the stopping criterion
   const int64_t ld = c->ld;
   const int form = c->o.form;
   RC(ensure_arena(c, P, krylov ? P * std::max(Keff, 1) : 1));
@@ -845,9 +850,37 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
     }
     HC(hipEventRecord(ev[3 + 3 * k], s));
     const int rr = c->r;
+    // Stopping criterion (Section 2.1): the chain changes slices k+1..P;
+    // keep their old values in the (now free) work block X.
+    const bool stop = c->o.stop_tol > 0;
+    if (stop) {
+      RC(ensure_arena(c, P - k, c->r));
+      HC(hipMemcpyAsync(c->X, c->Q + (int64_t)(k + 1) * ld,
+                        (size_t)(P - k) * ld * 8, hipMemcpyDeviceToDevice, s));
+    }
     RC(with_graph(c, gkey(3, k, rr), [&] { return chain(c, k); }));
     HC(hipEventRecord(ev[4 + 3 * k], s));
     if (k < 64) c->stats.rank[k] = c->r;
+    if (stop) {
+      // ||q^{k+1}_i - q^k_i||^2 for i = k+1..P (the others are unchanged)
+      // and ||q^{k+1}_i||^2 for i = 1..P.
+      HC(launch_sub(c->X, c->Q + (int64_t)(k + 1) * ld, c->X,
+                    (int64_t)(P - k) * ld, s));
+      HC(launch_colnorm2(c->X, ld, P - k, c->d, c->part, c->nrm, s));
+      HC(launch_colnorm2(c->Q + ld, ld, P, c->d, c->part, c->nrm + (P + 1), s));
+      HC(hipMemcpyAsync(c->h_nrm, c->nrm, 2 * (size_t)(P + 1) * 8,
+                        hipMemcpyDeviceToHost, s));
+      HC(hipStreamSynchronize(s));
+      double dmax = 0, qmax = 0;
+      for (int i = 0; i < P - k; ++i) dmax = std::max(dmax, c->h_nrm[i]);
+      for (int i = 0; i < P; ++i) qmax = std::max(qmax, c->h_nrm[P + 1 + i]);
+      const double rk = qmax > 0 ? std::sqrt(dmax) / std::sqrt(qmax) : 0.0;
+      if (k < 64) c->stats.residual[k] = rk;
+      if (rk <= c->o.stop_tol) {
+        Keff = k + 1;
+        break;
+      }
+    }
   }
   HC(launch_check_finite(c->Q + (int64_t)P * ld, c->d, c->ism + 2, s));
   HC(hipMemcpyAsync(c->h_ism + 2, c->ism + 2, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -882,8 +915,8 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
 
 // Section 2.1: windows (parallel steps) run one after the other, each from
 // the previous window's final state and with an empty subspace.  Timings
-// and fine point-steps are summed over the windows; ranks are the last
-// window's.
+// and fine point-steps are summed over the windows; iterations, ranks and
+// residuals are the last window's.
 static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
                       double* slices, int mem, bool krylov) {
   if (!u0 || !U_K) return set_error(c, PR_EINVAL, "null state pointer");
@@ -907,6 +940,7 @@ static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
   }
   acc.iterations = c->stats.iterations;
   std::memcpy(acc.rank, c->stats.rank, sizeof acc.rank);
+  std::memcpy(acc.residual, c->stats.residual, sizeof acc.residual);
   c->stats = acc;
   return PR_OK;
 }
@@ -1001,6 +1035,8 @@ extern "C" void pr_destroy(pr_ctx* c) {
     if (p) (void)hipFree(p);
   if (c->ism) (void)hipFree(c->ism);
   if (c->h_ism) (void)hipHostFree(c->h_ism);
+  if (c->nrm) (void)hipFree(c->nrm);
+  if (c->h_nrm) (void)hipHostFree(c->h_nrm);
   if (c->side) {
     (void)hipStreamSynchronize(c->side);
     (void)hipStreamDestroy(c->side);

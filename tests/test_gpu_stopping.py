@@ -1,0 +1,45 @@
+"""The stopping criterion of Section 2.1 on the GPU: r^k = max_i
+||q^{k+1}_i - q^k_i|| / max_i ||q^{k+1}_i|| after every iteration, the
+window ending at the first r^k <= stop_tol; against the oracle's run with
+the same tolerance."""
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.operators import Params
+from paper_1510_02237_amd import binding, workloads as W
+from gpu_cases import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["c1_64x32", "c1w_64x32"])
+def test_stops_where_the_oracle_stops(name):
+    prob, K, u0 = W.config(name)
+    prm = Params(**prob)
+    Kmax = 6
+    full = oracle.kse_parareal(u0, prm, K=Kmax)
+    r = full["residuals"]
+    tol = 0.5 * (r[1] + r[2])
+    assert r[2] < tol < r[1]
+    want = oracle.kse_parareal(u0, prm, K=Kmax, stop_tol=tol)
+    say(f"stopping {name} tol={tol:.3g}")
+    ctx = binding.Context.from_problem(prob, stop_tol=tol)
+    got = ctx.solve(u0, Kmax)
+    st = ctx.stats()
+    assert st["iterations"] == want["iterations"] == 3
+    assert rel_l2(got, want["q"][prm.P]) <= 1e-10
+    for a, b in zip(st["residual"], want["residuals"]):
+        assert abs(a - b) <= 1e-9 * b
+
+
+def test_fixed_K_reports_no_residual():
+    prob, K, u0 = W.config("c1_64x32")
+    ctx = binding.Context.from_problem(prob)
+    a = ctx.solve(u0, K)
+    st = ctx.stats()
+    assert st["iterations"] == K and st["residual"] == [0.0] * K
+    # a tolerance that is never reached gives the fixed-K result bitwise
+    b = binding.Context.from_problem(prob, stop_tol=1e-300).solve(u0, K)
+    assert np.array_equal(a, b)

@@ -150,13 +150,14 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(windows=3), "(T/(windows*P))/dt_f"),
     (dict(scheme=7), "scheme"),
     (dict(V=0.1), "V must be 0"),
+    (dict(stop_tol=-1.0), "stop_tol"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
     args = dict(nx=64, nz=32, c_s=1.0, U=0.1, dt_f=0.2 / 64, dt_g=2.0 / 64,
                 P=8)
     opts = {k: kw.pop(k) for k in list(kw) if k in ("n_sound", "tile_nt",
                                                    "tile_zc", "windows",
-                                                   "scheme", "V")}
+                                                   "scheme", "V", "stop_tol")}
     args.update(kw)
     rc, h = _create(lib, **args, **opts)
     assert rc == binding.PR_EINVAL and not h.value

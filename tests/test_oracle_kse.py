@@ -218,3 +218,38 @@ def test_c1_error_decreases_per_iteration():
     errs = [oracle.rel_l2(it[-1], ref) for it in out["iters"]]
     assert all(errs[k + 1] < 0.8 * errs[k] for k in range(K))
     assert out["ranks"] == [8, 15, 21]
+
+
+# ----------------------------------------------- stopping criterion r^k
+
+def test_residual_is_the_iterate_difference():
+    """r^k of Section 2.1 against differences of the stored iterates."""
+    prm = small(16, 8, P=4)
+    u0 = u0_for(prm)
+    out = oracle.kse_parareal(u0, prm, K=3, history=True)
+    it = out["iters"]
+    for k, r in enumerate(out["residuals"]):
+        num = max(np.linalg.norm(it[k + 1][i] - it[k][i]) for i in range(1, prm.P + 1))
+        den = max(np.linalg.norm(it[k + 1][i]) for i in range(1, prm.P + 1))
+        assert r == pytest.approx(num / den, rel=1e-14)
+
+
+def test_residual_vanishes_once_every_slice_is_exact():
+    """After P iterations all slices are the serial fine run (Section 2.1);
+    one more iteration changes nothing, so r^P = 0 exactly."""
+    prm = small(16, 8, P=4)
+    out = oracle.kse_parareal(u0_for(prm), prm, K=prm.P + 1)
+    assert out["residuals"][prm.P] == 0.0
+    assert out["residuals"][prm.P - 1] > 0.0
+
+
+def test_stopping_criterion_stops_at_first_small_residual():
+    prm = small(24, 16, P=6)
+    u0 = u0_for(prm)
+    full = oracle.kse_parareal(u0, prm, K=6)
+    tol = 0.5 * (full["residuals"][1] + full["residuals"][2])
+    assert full["residuals"][2] < tol < full["residuals"][1]
+    stop = oracle.kse_parareal(u0, prm, K=6, stop_tol=tol)
+    assert stop["iterations"] == 3
+    part = oracle.kse_parareal(u0, prm, K=3)
+    assert all(np.array_equal(a, b) for a, b in zip(stop["q"], part["q"]))
