@@ -49,6 +49,8 @@ class Params:
                 sixth-order centred advective flux; G: RK-3 with the
                 first-order upwind flux; both with second-order centred
                 acoustic fluxes and no damping)
+    coarse_order  order of the upwind advective flux of the split G: 1 (the
+                main runs of Section 3.2) or 3 (its less diffusive G)
     nu_f, nu_c  divergence-damping factors of F and G (eq. dampingCoeff)
     n_sound     acoustic substeps per coarse step (N_sound, Section 3.2)
     rank_tol    relative tolerance on |R_jj|/|R_11| for the rank of the
@@ -73,12 +75,15 @@ class Params:
     windows: int = 1
     scheme: str = "split"
     V: float = 0.0
+    coarse_order: int = 1
 
     def __post_init__(self):
         if self.scheme not in ("split", "rk3"):
             raise ValueError(f"unknown scheme {self.scheme!r}")
         if self.scheme == "split" and self.V != 0.0:
             raise ValueError("the split scheme advects along x only (V = 0)")
+        if self.coarse_order not in (1, 3):
+            raise ValueError("coarse_order must be 1 or 3")
 
     @property
     def dx(self):
@@ -143,6 +148,16 @@ def flux_centred6(q, axis):
     return (37.0 * (q + _at(q, 1, axis))
             - 8.0 * (_at(q, -1, axis) + _at(q, 2, axis))
             + (_at(q, -2, axis) + _at(q, 3, axis))) / 60.0
+
+
+def flux_upwind3(q, vel, axis):
+    """Third-order upwind advective flux of the Wicker-Skamarock family:
+    the fourth-order centred flux plus |vel| times a third-difference
+    dissipation term."""
+    c4 = 7.0 * (q + _at(q, 1, axis)) - (_at(q, -1, axis) + _at(q, 2, axis))
+    dis = ((_at(q, 2, axis) - _at(q, -1, axis))
+           - 3.0 * (_at(q, 1, axis) - q))
+    return vel / 12.0 * c4 + abs(vel) / 12.0 * dis
 
 
 def flux_upwind1(q, vel, axis):
@@ -236,11 +251,12 @@ def rhs_rk3_pair(q, prm: Params, coarse):
 
 def coarse_slow_tendency(q, prm: Params):
     """Slow (advective) tendency of the partially split coarse scheme:
-    first-order upwind advection, evaluated once per coarse step and held
-    fixed over its acoustic substeps (Section 3.2)."""
+    first-order upwind advection (third-order with ``coarse_order`` 3, the
+    less diffusive G of Section 3.2), evaluated once per coarse step and
+    held fixed over its acoustic substeps (Section 3.2)."""
     X = 1
-    return np.stack([-flux_div(flux_upwind1(f, prm.U, X), prm.dx, X)
-                     for f in q])
+    flux = flux_upwind3 if prm.coarse_order == 3 else flux_upwind1
+    return np.stack([-flux_div(flux(f, prm.U, X), prm.dx, X) for f in q])
 
 
 def acoustic_substep(q, R, dtau, prm: Params):

@@ -129,3 +129,91 @@ def test_serial_fine_is_F_composed():
     b = prop.fine_F(prop.fine_F(prop.fine_F(q0, prm), prm), prm)
     assert np.array_equal(a, b)
     assert np.array_equal(prop.fine_F(q0, prm, 3 * prm.n_f), a)
+
+
+# ------------------------------------- the less diffusive G of Section 3.2
+
+def _a3(tx, dx, U):
+    """Third-order upwind derivative from its point weights (1, -6, 3, 2)/6
+    at i-2..i+1 for U >= 0, mirrored for U < 0."""
+    e = lambda m: np.exp(1j * m * tx)
+    if U >= 0:
+        return (e(-2) - 6 * e(-1) + 3 + 2 * e(1)) / (6 * dx)
+    return (-2 * e(-1) - 3 + 6 * e(1) - e(2)) / (6 * dx)
+
+
+def test_upwind3_is_third_order():
+    from oracle import operators as ops
+    errs = []
+    for n in (32, 64, 128):
+        x = (np.arange(n) + 0.5) / n
+        f = np.sin(2 * np.pi * x) + 0.3 * np.cos(6 * np.pi * x)
+        exact = 2 * np.pi * np.cos(2 * np.pi * x) - 1.8 * np.pi * np.sin(6 * np.pi * x)
+        for vel in (0.7, -0.7):
+            q = np.tile(f, (4, 1))
+            d = ops.flux_div(ops.flux_upwind3(q, vel, 1), 1.0 / n, 1)[0] / vel
+            errs.append((n, vel, np.abs(d - exact).max()))
+    for vel in (0.7, -0.7):
+        e = [x[2] for x in errs if x[1] == vel]
+        o = [np.log2(e[i] / e[i + 1]) for i in range(2)]
+        assert min(o) > 2.9, (vel, o)
+
+
+@pytest.mark.parametrize("U", [0.1, -0.2])
+@pytest.mark.parametrize("kx,kz", [(1, 0), (2, 3), (9, -4), (16, 8)])
+def test_less_diffusive_G_single_mode(U, kx, kz):
+    """One coarse step with the third-order slow tendency is the product of
+    the substep matrices with R frozen, as for the first-order G."""
+    prm = _prm(U=U, n_sound=8, nu_c=0.005, coarse_order=3)
+    v = np.array([1.0, 0.2 - 0.5j, -0.3j])
+    got = apply_complex(lambda q: prop.coarse_G(q, prm, 2), prm, kx, kz, v)
+    s = _symbols(2 * np.pi * kx / prm.nx, 2 * np.pi * kz / prm.nz,
+                 prm.dx, prm.dz, prm.U)
+    s["a1"] = _a3(2 * np.pi * kx / prm.nx, prm.dx, prm.U)
+    Y = _coarse_step_from(prm, s)
+    want = np.linalg.matrix_power(Y, 2) @ v
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
+def _coarse_step_from(prm, s):
+    dtau = prm.dt_g / prm.n_sound
+    ax = prm.nu_c * prm.dx ** 2 / dtau
+    az = prm.nu_c * prm.dz ** 2 / dtau
+    c = prm.c_s
+    Rs = -prm.U * s["a1"]
+    Y = np.eye(3, dtype=complex)
+    for _ in range(prm.n_sound):
+        u, w, p = Y
+        un = u + dtau * (Rs * np.eye(3)[0] - c * s["dx2"] * p
+                         + ax * (s["gxx"] * u + s["gxz"] * w))
+        wn = w + dtau * (Rs * np.eye(3)[1] - c * s["dz2"] * p
+                         + az * (s["gzz"] * w + s["gxz"] * u))
+        pn = p + dtau * (Rs * np.eye(3)[2] - c * (s["dx2"] * un + s["dz2"] * wn))
+        Y = np.array([un, wn, pn])
+    return Y
+
+
+def _worst_less_diffusive(nu_c):
+    """Largest spectral radius of one coarse step with the third-order slow
+    tendency, N_sound = 8, on the 64 x 32 grid at coarse CFL 2, U = 0.1."""
+    prm = _prm(nx=64, nz=32, U=0.1, dt_f=0.2 / 64, dt_g=2.0 / 64, n_sound=8,
+               nu_f=0.0, nu_c=nu_c, coarse_order=3)
+    worst = 0.0
+    for kx in range(prm.nx):
+        for kz in range(prm.nz):
+            s = _symbols(2 * np.pi * kx / prm.nx, 2 * np.pi * kz / prm.nz,
+                         prm.dx, prm.dz, prm.U)
+            s["a1"] = _a3(2 * np.pi * kx / prm.nx, prm.dx, prm.U)
+            worst = max(worst, np.abs(np.linalg.eigvals(_coarse_step_from(prm, s))).max())
+    return worst
+
+
+def test_less_diffusive_G_is_unstable_under_these_readings():
+    """Section 3.2's less diffusive G (third-order slow tendency, nu_c =
+    0.005, N_sound = 8) grows under the readings taken here (frozen slow
+    tendency over forward-backward substeps): forward Euler on a
+    third-order upwind tendency amplifies low wavenumbers, whose upwind
+    damping is only fourth order in the wavenumber.  More divergence
+    damping does not remove it."""
+    assert _worst_less_diffusive(0.005) > 1.1
+    assert _worst_less_diffusive(0.1) > 1.005
