@@ -14,7 +14,10 @@
 // One launch performs up to kCoarseMaxSubPerLaunch substeps: a workgroup
 // loads a TX x TZ tile plus a halo of 2 cells per substep (and one more
 // column on each side when it evaluates R) into LDS, runs the substeps
-// there and writes the tile interior.  The LDS region carries one more
+// there and writes the tile interior.  u and w are double-buffered in LDS
+// (the momentum update writes the other buffer, so two barriers per
+// substep suffice) and each thread keeps its own points' values in
+// registers.  The LDS region carries one more
 // ring of cells that is never written with valid data, so every neighbour
 // is a fixed offset and the points near the edge (whose results are
 // discarded) need no clamping.  Each thread owns the same MPT points in
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   constexpr int SX = RXM + 2;                     // padded LDS row stride
   constexpr int LDSN = (RZM + 2) * SX;
   constexpr int MPT = (RXM * RZM + NT - 1) / NT;  // points per thread
-  __shared__ double su[LDSN], sw[LDSN], sp[LDSN];
+  __shared__ double su[LDSN], sw[LDSN], sp[LDSN], su2[LDSN], sw2[LDSN];
   const int nx = L.nx, nz = L.nz;
   const int64_t n = (int64_t)nx * nz;
   const int xtiles = (nx + TX - 1) / TX;
@@ -61,7 +64,7 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   const CoarseCoef k = L.c;
 
   // Zero the whole LDS region once (the outer ring stays zero).
-  for (int q = t; q < LDSN; q += NT) su[q] = sw[q] = sp[q] = 0.0;
+  for (int q = t; q < LDSN; q += NT) su[q] = sw[q] = sp[q] = su2[q] = sw2[q] = 0.0;
 
   int qi[MPT];       // LDS index of each owned point, -1 if none
   int64_t gi[MPT];   // global index of each owned point (wrapped)
@@ -132,52 +135,54 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   }
 
   const double dtau = k.dtau;
+  double* cu = su;   // u, w of the current substep
+  double* cw = sw;
+  double* nu_ = su2; // u, w being written
+  double* nw_ = sw2;
   for (int s = 0; s < L.nsub; ++s) {
-    double un[MPT], wn[MPT];
 #pragma unroll
     for (int m = 0; m < MPT; ++m) {
-      un[m] = wn[m] = 0.0;
       if (qi[m] < 0) continue;
       const int q = qi[m];
-      const double u = su[q], w = sw[q];
+      const double u = vu[m], w = vw[m];
       const double dpx = sp[q + 1] - sp[q - 1];
       const double dpz = sp[q + SX] - sp[q - SX];
-      const double gxx = (su[q + 1] + su[q - 1]) - 2.0 * u;
-      const double gzz = (sw[q + SX] + sw[q - SX]) - 2.0 * w;
-      const double wx = (sw[q + SX + 1] - sw[q - SX + 1]) -
-                        (sw[q + SX - 1] - sw[q - SX - 1]);
-      const double uz = (su[q + SX + 1] - su[q + SX - 1]) -
-                        (su[q - SX + 1] - su[q - SX - 1]);
-      un[m] = u + dtau * (Ru[m] - k.cx2 * dpx + k.kxx * gxx + k.kxzu * wx);
-      wn[m] = w + dtau * (Rw[m] - k.cz2 * dpz + k.kzz * gzz + k.kxzw * uz);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < MPT; ++m) {
-      if (qi[m] >= 0) {
-        su[qi[m]] = un[m];
-        sw[qi[m]] = wn[m];
-      }
+      const double gxx = (cu[q + 1] + cu[q - 1]) - 2.0 * u;
+      const double gzz = (cw[q + SX] + cw[q - SX]) - 2.0 * w;
+      const double wx = (cw[q + SX + 1] - cw[q - SX + 1]) -
+                        (cw[q + SX - 1] - cw[q - SX - 1]);
+      const double uz = (cu[q + SX + 1] - cu[q + SX - 1]) -
+                        (cu[q - SX + 1] - cu[q - SX - 1]);
+      vu[m] = u + dtau * (Ru[m] - k.cx2 * dpx + k.kxx * gxx + k.kxzu * wx);
+      vw[m] = w + dtau * (Rw[m] - k.cz2 * dpz + k.kzz * gzz + k.kxzw * uz);
+      nu_[q] = vu[m];
+      nw_[q] = vw[m];
     }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MPT; ++m) {
       if (qi[m] < 0) continue;
       const int q = qi[m];
-      const double dux = su[q + 1] - su[q - 1];
-      const double dwz = sw[q + SX] - sw[q - SX];
-      sp[q] = sp[q] + dtau * (Rp[m] - k.cx2 * dux - k.cz2 * dwz);
+      const double dux = nu_[q + 1] - nu_[q - 1];
+      const double dwz = nw_[q + SX] - nw_[q - SX];
+      vp[m] = vp[m] + dtau * (Rp[m] - k.cx2 * dux - k.cz2 * dwz);
+      sp[q] = vp[m];
     }
     __syncthreads();
+    double* tu = cu;  // the buffers written become the current ones
+    cu = nu_;
+    nu_ = tu;
+    double* tw = cw;
+    cw = nw_;
+    nw_ = tw;
   }
 
 #pragma unroll
   for (int m = 0; m < MPT; ++m) {
     if (cflag[m]) {
-      const int q = qi[m];
-      out[gi[m]] = su[q];
-      out[n + gi[m]] = sw[q];
-      out[2 * n + gi[m]] = sp[q];
+      out[gi[m]] = vu[m];
+      out[n + gi[m]] = vw[m];
+      out[2 * n + gi[m]] = vp[m];
     }
   }
 }
