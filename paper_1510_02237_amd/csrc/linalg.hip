@@ -343,6 +343,9 @@ __global__ __launch_bounds__(256) void k_gemm_tn_mfma(
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m0 = tm * TN_T + (wv >> 1) * 32;
   const int n0 = tn * TN_T + (wv & 1) * 32;
+  // A quarter wholly beyond M or N has nothing to compute (N <= 32 leaves
+  // half the waves of every tile idle); no barrier follows.
+  if (m0 >= M || n0 >= N) return;
   const int64_t xs = (int64_t)split * kc;
   const int64_t xe = xs + kc < d ? xs + kc : d;
   const int r16 = lane & 15, kq = lane >> 4;

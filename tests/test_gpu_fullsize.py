@@ -96,3 +96,44 @@ def test_full_size_solve_matches_oracle_fixture(c2):
     want = np.array(fx["sample_value"])
     assert np.abs(flat[idx] - want).max() <= 1e-10 * fx["final_max"]
     assert abs(np.linalg.norm(flat) - fx["final_norm2"]) <= 1e-10 * fx["final_norm2"]
+
+
+def _c5_reduced(n_f, n_g, P):
+    """The 4096 x 1024 grid of the largest workload with short slices, so
+    that the oracle can follow: n_f fine and n_g coarse steps per slice."""
+    prob, K, u0 = W.config("c5_4096x1024")
+    prob = dict(prob, P=P, dt_g=prob["dt_f"] * n_f / n_g)
+    prob["T"] = P * n_f * prob["dt_f"]
+    return prob, u0
+
+
+def test_c5_grid_sweep_and_coarse_match_oracle():
+    """Fine sweep (2 RK-3 steps) and coarse step on the 4096 x 1024 grid."""
+    torch = pytest.importorskip("torch")
+    prob, u0 = _c5_reduced(n_f=2, n_g=1, P=1)
+    prm = Params(**prob)
+    say("4096x1024 sweep and coarse step")
+    ctx = binding.Context.from_problem(prob)
+    got = ctx.fine_sweep(torch.from_numpy(u0[None]).cuda()).cpu().numpy()[0]
+    assert rel_l2(got, oracle.fine_F(u0, prm)) <= 1e-12
+    assert rel_l2(ctx.coarse_step(u0), oracle.coarse_G(u0, prm)) <= 1e-12
+
+
+def test_c5_grid_reduced_solve_properties():
+    """P = 8, K = 2 on the 4096 x 1024 grid (Section 2.1 and 2.2 facts):
+    K = P is the serial fine run bitwise, the solve is homogeneous, and the
+    basis grows by at most P - k vectors in iteration k. (Slices of ten
+    fine steps give nearly dependent coarse states, so the rank test may
+    keep fewer than P of the first batch.)"""
+    torch = pytest.importorskip("torch")
+    prob, u0 = _c5_reduced(n_f=10, n_g=1, P=8)
+    say("4096x1024 reduced solve")
+    u0d = torch.from_numpy(u0).cuda()
+    ctx = binding.Context.from_problem(prob)
+    a = ctx.solve(u0d, 2).cpu().numpy()
+    r = ctx.stats()["rank"]
+    assert len(r) == 2 and 0 < r[0] <= 8 and r[0] <= r[1] <= r[0] + 7
+    assert np.array_equal(ctx.solve(2.0 * u0d, 2).cpu().numpy(), 2.0 * a)
+    ref = ctx.serial_fine(u0d).cpu().numpy()
+    assert np.array_equal(ctx.solve(u0d, 8).cpu().numpy(), ref)
+    assert rel_l2(a, ref) < rel_l2(ctx.solve(u0d, 0).cpu().numpy(), ref)
