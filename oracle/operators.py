@@ -10,13 +10,20 @@ operator here is written that way: an interface flux is computed on the
 x- (or z-) faces, then differenced.  The flux stencils are those of the
 Wicker-Skamarock family the paper cites for orders one to six.
 
-The acoustic-advection system (eq. acousticAd), with constant advection
-velocity U along x and the paper's divergence damping (the modified momentum
-equations of Section 3.2, coefficients of eq. dampingCoeff), reads
+The acoustic-advection system (eq. acousticAd) with the paper's divergence
+damping (the modified momentum equations of Section 3.2, coefficients of
+eq. dampingCoeff) reads, for an advection velocity (U_x, U_z),
 
-    u_t = -U u_x - c_s p_x         + alpha_1 (div u)_x
-    w_t = -U w_x - c_s p_z         + alpha_2 (div u)_z
-    p_t = -U p_x - c_s (u_x + w_z)
+    u_t = -U_x u_x - U_z u_z - c_s p_x         + alpha_1 (div u)_x
+    w_t = -U_x w_x - U_z w_z - c_s p_z         + alpha_2 (div u)_z
+    p_t = -U_x p_x - U_z p_z - c_s (u_x + w_z)
+
+The velocity is (U + gamma (z - Lz/2), V - gamma (x - Lx/2)): a constant
+part plus the solid-body rotation of eq. adVel (gamma = pi there, U = V = 0).
+Its x-component depends on z only and its z-component on x only, so it is
+divergence-free, the advective form equals the flux form, and the velocity
+on an x-face (a z-face) is the exact value of the row (the column): no
+interpolation to the faces is needed.
 
 Array convention: a field is an (nz, nx) array, x along axis 1.
 ``_at(q, m, axis)`` returns the field shifted so that entry i holds q_{i+m}
@@ -33,9 +40,10 @@ class Params:
     """One KSE-Parareal problem on the periodic unit square.
 
     nx, nz      cells along x and z (dx = Lx/nx, dz = Lz/nz)
-    c_s, U      sound speed and constant advection velocity along x
-    V           constant advection velocity along z (scheme "rk3" only; the
-                Section 3.2 runs advect along x)
+    c_s         sound speed
+    U, V        constant part of the advection velocity along x and z
+    gamma       rotation rate of the solid-body part of the velocity (eq.
+                adVel: gamma = pi, one revolution in T = 2); split scheme only
     dt_f, dt_g  fine step (delta t) and coarse step (Delta t)
     P           number of time slices N_c of one window (parallel step)
     T           end time
@@ -51,6 +59,9 @@ class Params:
                 acoustic fluxes and no damping)
     coarse_order  order of the upwind advective flux of the split G: 1 (the
                 main runs of Section 3.2) or 3 (its less diffusive G)
+    fine_acoustic_order  order of the centred acoustic fluxes of the split
+                F: 4, or 2 (Section 3 computes the acoustic fluxes of both
+                propagators to second order)
     nu_f, nu_c  divergence-damping factors of F and G (eq. dampingCoeff)
     n_sound     acoustic substeps per coarse step (N_sound, Section 3.2)
     rank_tol    relative tolerance on |R_jj|/|R_11| for the rank of the
@@ -76,14 +87,19 @@ class Params:
     scheme: str = "split"
     V: float = 0.0
     coarse_order: int = 1
+    gamma: float = 0.0
+    fine_acoustic_order: int = 4
 
     def __post_init__(self):
         if self.scheme not in ("split", "rk3"):
             raise ValueError(f"unknown scheme {self.scheme!r}")
-        if self.scheme == "split" and self.V != 0.0:
-            raise ValueError("the split scheme advects along x only (V = 0)")
+        if self.scheme == "rk3" and self.gamma != 0.0:
+            raise ValueError("the Section 3.1 pair advects with a constant "
+                             "velocity (gamma = 0)")
         if self.coarse_order not in (1, 3):
             raise ValueError("coarse_order must be 1 or 3")
+        if self.fine_acoustic_order not in (2, 4):
+            raise ValueError("fine_acoustic_order must be 2 or 4")
 
     @property
     def dx(self):
@@ -118,6 +134,20 @@ def _integer_ratio(a, b):
     if n < 1 or abs(n * b - a) > 1e-9 * abs(a):
         raise ValueError(f"{a} is not an integer multiple of {b}")
     return n
+
+
+def velocity_x(prm: Params):
+    """x-component of the advection velocity on the x-faces of each row,
+    shape (nz, 1): U + gamma (z_j - Lz/2) at the row's height z_j."""
+    z = (np.arange(prm.nz) + 0.5) * prm.dz
+    return (prm.U + prm.gamma * (z - 0.5 * prm.Lz))[:, None]
+
+
+def velocity_z(prm: Params):
+    """z-component of the advection velocity on the z-faces of each column,
+    shape (1, nx): V - gamma (x_i - Lx/2) at the column's position x_i."""
+    x = (np.arange(prm.nx) + 0.5) * prm.dx
+    return (prm.V - prm.gamma * (x - 0.5 * prm.Lx))[None, :]
 
 
 def _at(q, m, axis):
@@ -207,24 +237,36 @@ def grad_div(u, w, dx, dz):
 # Right-hand sides.
 # ---------------------------------------------------------------------------
 
+def advection(f, prm: Params, flux):
+    """Flux-form advective tendency (U_x f)_x + (U_z f)_z of one field with
+    the upwind interface flux ``flux`` in both directions.  The z-term is
+    left out when the velocity has no z-component (V = gamma = 0)."""
+    X, Z = 1, 0
+    a = flux_div(flux(f, velocity_x(prm), X), prm.dx, X)
+    if prm.V != 0.0 or prm.gamma != 0.0:
+        a = a + flux_div(flux(f, velocity_z(prm), Z), prm.dz, Z)
+    return a
+
+
 def rhs_fine(q, prm: Params):
     """f(q) of the fine propagator F (Section 3.2 and eq. acousticAd):
-    fifth-order upwind advection, fourth-order centred acoustic fluxes and
+    fifth-order upwind advection, fourth-order (or, with
+    fine_acoustic_order 2, second-order) centred acoustic fluxes and
     divergence damping with alpha = nu_f * h^2 / dt_f (eq. dampingCoeff,
     tau = delta t)."""
     X, Z = 1, 0
     u, w, p = q
-    dx, dz, c, U = prm.dx, prm.dz, prm.c_s, prm.U
+    dx, dz, c = prm.dx, prm.dz, prm.c_s
+    ac = flux_centred4 if prm.fine_acoustic_order == 4 else flux_centred2
     ax = prm.nu_f * dx * dx / prm.dt_f
     az = prm.nu_f * dz * dz / prm.dt_f
     gdx, gdz = grad_div(u, w, dx, dz)
-    fu = (-flux_div(flux_upwind5(u, U, X), dx, X)
-          - c * flux_div(flux_centred4(p, X), dx, X) + ax * gdx)
-    fw = (-flux_div(flux_upwind5(w, U, X), dx, X)
-          - c * flux_div(flux_centred4(p, Z), dz, Z) + az * gdz)
-    fp = (-flux_div(flux_upwind5(p, U, X), dx, X)
-          - c * (flux_div(flux_centred4(u, X), dx, X)
-                 + flux_div(flux_centred4(w, Z), dz, Z)))
+    fu = (-advection(u, prm, flux_upwind5)
+          - c * flux_div(ac(p, X), dx, X) + ax * gdx)
+    fw = (-advection(w, prm, flux_upwind5)
+          - c * flux_div(ac(p, Z), dz, Z) + az * gdz)
+    fp = (-advection(p, prm, flux_upwind5)
+          - c * (flux_div(ac(u, X), dx, X) + flux_div(ac(w, Z), dz, Z)))
     return np.stack([fu, fw, fp])
 
 
@@ -254,9 +296,8 @@ def coarse_slow_tendency(q, prm: Params):
     first-order upwind advection (third-order with ``coarse_order`` 3, the
     less diffusive G of Section 3.2), evaluated once per coarse step and
     held fixed over its acoustic substeps (Section 3.2)."""
-    X = 1
     flux = flux_upwind3 if prm.coarse_order == 3 else flux_upwind1
-    return np.stack([-flux_div(flux(f, prm.U, X), prm.dx, X) for f in q])
+    return np.stack([-advection(f, prm, flux) for f in q])
 
 
 def acoustic_substep(q, R, dtau, prm: Params):

@@ -7,8 +7,9 @@ nothing but numpy.
 
 State layout: float64 array (3, nz, nx), fields (u, w, p), x fastest.
 
-Parameter readings (the paper's own test case uses a rotating flow; these
-workloads use constant U along x):
+Parameter readings of the constant-velocity workloads (advection by a
+constant U along x; the paper's own rotating-flow runs are built by
+``rotation_problem``):
   * fine step  dt_f = 0.2 * min(dx, dz) / c_s   (fine CFL 0.2, Section 3.2)
   * coarse step dt_g = 10 * dt_f                 (coarse CFL 2.0, Table 1)
   * nu_f = 0.005, nu_c = 0.1 (Section 3.2)
@@ -58,6 +59,21 @@ def one_coarse_step_windows(prob):
     if M < 1 or abs(M - m) > 1e-9 * m:
         raise ValueError("T / (P dt_g) is not an integer")
     return M
+
+
+def rotation_problem(n, P, cfl_c, T=2.0):
+    """The solid-body-rotation runs of Section 3.2 on n x n cells: velocity
+    pi (z - 1/2, -(x - 1/2)) (eq. adVel, one revolution in T = 2), c_s = 30,
+    fine CFL 0.2, coarse CFL ``cfl_c`` (2 or 4 in Tables 1-2), N_sound = 4,
+    nu_f = 0.005, nu_c = 0.1, second-order acoustic fluxes in both
+    propagators, and the paper's decomposition: every slice is one coarse
+    step, windows of P slices cover [0, T]."""
+    ratio = int(round(cfl_c / 0.2))
+    prob = problem(n, n, P, U=0.0, c_s=30.0, T=T, cfl_f=0.2,
+                   coarse_ratio=ratio, n_sound=4)
+    prob.update(gamma=math.pi, fine_acoustic_order=2)
+    prob["windows"] = one_coarse_step_windows(prob)
+    return prob
 
 
 def _cell_centres(nx, nz):
@@ -150,12 +166,29 @@ CONFIGS = {
     "demo_40x40": dict(nx=40, nz=40, P=6, K=5, U=1.0, V=1.0, c_s=1.0,
                        ic=dict(kind="cosine_bell"), scheme="rk3",
                        dt_g=1.0 / 72.0, coarse_ratio=6, windows=12),
+    # The paper's own runs (Section 3.2, Figures vorticity to energy, Table
+    # 2): solid-body rotation at coarse CFL 4 with N_p = 6 slices per
+    # window, 100 windows over T = 2, the cosine bell in u at (0.5, 0.65).
+    "rot_40x40": dict(nx=40, nz=40, P=6, K=2, rotation=dict(cfl_c=4.0),
+                      ic=dict(kind="cosine_bell", centre=(0.5, 0.65))),
+    "rot_80x80": dict(nx=80, nz=80, P=6, K=2, rotation=dict(cfl_c=4.0),
+                      ic=dict(kind="cosine_bell", centre=(0.5, 0.65))),
 }
+
+# The cells of Tables 1 and 2 of Section 3.2 on 40 x 40 cells: (coarse CFL,
+# slices per window, iterations per window).
+PAPER_TABLE_CELLS = tuple(
+    (cc, P, K) for cc in (2.0, 4.0)
+    for P, kmax in ((4, 2), (6, 3), (8, 4)) for K in range(1, kmax + 1))
 
 
 def config(name):
     """(problem dict, K, initial state) of a named workload."""
     c = CONFIGS[name]
+    if "rotation" in c:
+        prob = rotation_problem(c["nx"], c["P"], **c["rotation"])
+        return prob, c["K"], ic_cosine_bell(c["nx"], c["nz"],
+                                            centre=c["ic"]["centre"])
     prob = problem(c["nx"], c["nz"], c["P"], U=c["U"], c_s=c.get("c_s", 1.0),
                    n_sound=1 if c.get("scheme") == "rk3" else None)
     if c.get("windows") == "one_step":

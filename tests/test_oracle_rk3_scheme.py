@@ -35,9 +35,9 @@ def _prm(**kw):
     return Params(**base)
 
 
-def test_split_scheme_rejects_V():
+def test_rk3_scheme_rejects_rotation():
     with pytest.raises(ValueError):
-        Params(nx=8, nz=8, c_s=1.0, U=0.1, V=0.1, dt_f=1e-3, dt_g=1e-2, P=1)
+        _prm(gamma=1.0)
 
 
 def test_centred6_is_sixth_order():
