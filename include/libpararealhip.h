@@ -80,7 +80,8 @@ enum { PR_FORM_BATCHED = 0, PR_FORM_PLAIN = 1, PR_FORM_STAGEWISE = 2 };
  *     fifth-order upwind advection, fourth-order centred acoustics and
  *     divergence damping (nu_f).  G is partially split forward Euler with
  *     N_sound forward-backward acoustic substeps and damping (nu_c).
- *     Advection is along x (U).
+ *     The advection velocity is (U + gamma (z - Lz/2), V - gamma (x - Lx/2))
+ *     with V and gamma from pr_opts (eq. adVel); by default (U, 0).
  *   PR_SCHEME_RK3: those of the instability example of Section 3.1.  F is
  *     RK-3 with the sixth-order centred advective flux; G is RK-3 with the
  *     first-order upwind flux (step dt_g).  Both use second-order centred
@@ -124,8 +125,9 @@ typedef struct pr_opts {
                              coarse step, as in the paper's runs.  The server
                              accepts only 1.                                   */
   int32_t scheme;         /* PR_SCHEME_SPLIT (default) or PR_SCHEME_RK3       */
-  double V;               /* advection velocity along z; must be 0 with
-                             PR_SCHEME_SPLIT (default 0)                       */
+  double V;               /* constant part of the advection velocity along z
+                             (default 0); U (an argument of pr_create) is the
+                             one along x                                        */
   double stop_tol;        /* stopping criterion of Section 2.1: 0 (default)
                              runs exactly K iterations; > 0 ends a window
                              after the first iteration k whose error
@@ -135,6 +137,24 @@ typedef struct pr_opts {
                              maximum.  Costs one copy and two norm passes
                              over the iterates per iteration.  The server
                              accepts only 0.                                   */
+  double gamma;           /* rotation rate of the solid-body part of the
+                             advection velocity, PR_SCHEME_SPLIT only: the
+                             velocity is (U + gamma (z - Lz/2), V - gamma
+                             (x - Lx/2)), eq. adVel of Section 3.2 with
+                             gamma = pi and U = V = 0 (one revolution in
+                             T = 2).  Default 0.                               */
+  int32_t fine_acoustic_order; /* order of the centred acoustic differences
+                             of F in PR_SCHEME_SPLIT: 4 (default) or 2
+                             (Section 3 computes the acoustic fluxes of both
+                             propagators to second order).  PR_SCHEME_RK3
+                             always uses 2.
+
+                             With V != 0, gamma != 0 or fine_acoustic_order
+                             = 2, F runs in PR_FORM_STAGEWISE (three stage
+                             launches per RK-3 step with per-row and
+                             per-column advective weights) and the slow
+                             tendency of G comes from a separate launch;
+                             the server accepts none of these.               */
 } pr_opts;
 
 typedef struct pr_ctx pr_ctx;
@@ -159,8 +179,14 @@ void pr_opts_default(pr_opts* o);
  * the fine semi-discretisation) and G (one partially split coarse step),
  * Section 3 and Section 3.2.  Scans every discrete Fourier mode when
  * nx*nz <= 65536, else a 256 x 256 sample of phase angles that contains the
- * axis modes.  Writes the largest spectral radii found.  Returns PR_EINVAL
- * for bad parameters, else PR_OK.  Never touches the GPU. */
+ * axis modes.  Writes the largest spectral radii found.  The scan is exact
+ * for a constant velocity.  With pr_opts.gamma != 0 the coefficients vary
+ * in space and no Fourier mode is invariant: the radii are then those of
+ * the symbols frozen at the four extreme velocity pairs of the grid (the
+ * largest and smallest x-velocity of a row with the largest and smallest
+ * z-velocity of a column), a local estimate that may exceed 1 for a stable
+ * propagator.  Returns PR_EINVAL for bad parameters, else PR_OK.  Never
+ * touches the GPU. */
 int pr_check_stability(const pr_grid* g, double c_s, double U, double dt_f,
                        double dt_g, const pr_opts* o, double* rho_f,
                        double* rho_g);
@@ -176,8 +202,12 @@ int pr_footprint(const pr_grid* g, int32_t P, int32_t K, size_t* bytes);
  * device.  pr_create_ex takes options and a hipStream_t (NULL = default
  * stream).  PR_EINVAL: nx or nz < 8, P < 1, non-positive lengths or steps,
  * (T/P)/dt_f or (T/P)/dt_g not an integer within 1e-9 relative,
- * n_sound < 1.  PR_EUNSTABLE: pr_check_stability finds rho > 1 + 1e-12.
- * Device memory is allocated lazily by the first call that needs it. */
+ * n_sound < 1, an option out of range.  PR_EUNSTABLE: pr_check_stability
+ * finds rho > 1 + 1e-12 for a constant velocity (gamma = 0; with gamma != 0
+ * the frozen-coefficient estimate is not enforced).  Device memory is
+ * allocated lazily by the first call that needs it, except the per-row and
+ * per-column stage weights ((nx + nz) * 14 doubles), allocated here when the
+ * options need them. */
 int pr_create(const pr_grid* g, double c_s, double U, double dt_f,
               double dt_g, int32_t P, pr_ctx** out);
 int pr_create_ex(const pr_grid* g, double c_s, double U, double dt_f,

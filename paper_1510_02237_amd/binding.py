@@ -44,7 +44,9 @@ class Opts(ctypes.Structure):
                 ("form", ctypes.c_int32), ("skip_converged", ctypes.c_int32),
                 ("tile_nt", ctypes.c_int32), ("tile_zc", ctypes.c_int32),
                 ("windows", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("V", ctypes.c_double), ("stop_tol", ctypes.c_double)]
+                ("V", ctypes.c_double), ("stop_tol", ctypes.c_double),
+                ("gamma", ctypes.c_double),
+                ("fine_acoustic_order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -231,7 +233,9 @@ class Context:
         o = dict(nu_f=prob["nu_f"], nu_c=prob["nu_c"],
                  n_sound=prob["n_sound"], rank_tol=prob["rank_tol"],
                  windows=prob.get("windows", 1),
-                 scheme=prob.get("scheme", "split"), V=prob.get("V", 0.0))
+                 scheme=prob.get("scheme", "split"), V=prob.get("V", 0.0),
+                 gamma=prob.get("gamma", 0.0),
+                 fine_acoustic_order=prob.get("fine_acoustic_order", 4))
         o.update(opts)
         return cls(prob["nx"], prob["nz"], prob["c_s"], prob["U"],
                    prob["dt_f"], prob["dt_g"], prob["P"], T=prob["T"], **o)

@@ -22,8 +22,14 @@ struct pr_ctx {
   int64_t ld = 0;  // padded state stride of internal buffers (multiple of 64)
   prh::FineCoef fc{};
   prh::CoarseCoef cc{};
-  prh::Rk3Coef rf{}, rg{};  // scheme PR_SCHEME_RK3: fine and coarse weights
-  bool rk3 = false;
+  // Stage kernels with advective weights per row and per column: the
+  // Section 3.1 pair (rk3), and the split scheme with a z-velocity, a
+  // rotation or second-order fine acoustics (tables_f: F runs as stages;
+  // tables_g: the slow tendency of G comes from the stage kernel).
+  prh::StageCoef sf{}, sg{};
+  std::vector<double> h_tabs;  // F x, F z, G x, G z weights ([n][7] each)
+  double* tabs = nullptr;      // device copy of h_tabs
+  bool rk3 = false, tables_f = false, tables_g = false;
   int sgn = 1;
   std::vector<int> coarse_chunks;  // substeps per launch within a coarse step
 
@@ -47,8 +53,9 @@ struct pr_ctx {
   double* X = nullptr;    // wcap: new raw columns (projected in place)
   double* DX = nullptr;   // wcap: their F - G images
   double* Yb = nullptr;   // wcap: CholQR intermediate, batched-G pong
-  double* Rb = nullptr;   // wcap: frozen slow tendency when N_sound > 4, or
-                          // the step buffer of the RK-3 coarse propagator
+  double* Rb = nullptr;   // wcap: frozen slow tendency when N_sound > 4 or
+                          // tables_g, or the step buffer of the RK-3 coarse
+                          // propagator
   double* st = nullptr;   // kSingle single states
   double* S = nullptr;    // rcap basis vectors
   double* D = nullptr;    // rcap vectors F(s_j) - G(s_j)
@@ -97,7 +104,8 @@ int run_sweep(pr_ctx* c, const double* in, int64_t in_stride, double* out,
               int form);
 // Coarse propagator over one slice for ns states at stride `stride`:
 // out = G(in); pa, pb: ping buffers (ns states each), R: slow-tendency
-// buffer (ns states) needed when N_sound > 4.  in must not alias out.
+// buffer (ns states) needed when N_sound > 4, tables_g or rk3.  in must not
+// alias out.
 int run_coarse(pr_ctx* c, const double* in, double* out, int ns,
                int64_t stride, double* pa, double* pb, double* R);
 // Appends span of b columns X0 (stride ld) with fine images FX0 (stride ld)

@@ -83,25 +83,28 @@ hipError_t launch_fine_stage(const double* in, int64_t in_stride,
                              int sgn, hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// The propagator pair of the instability example (Section 3.1, scheme
-// PR_SCHEME_RK3): RK-3 stages of
-//   f(q)_field = sum_{m=-3..3} (wx[m+3] q(i+m, j) + wz[m+3] q(i, j+m))
-//              - acoustic centred differences,
-// with the advective weights of the sixth-order centred flux (F) or the
-// first-order upwind flux (G), advection velocity included.
+// Stage kernel with advective weights per row and per column (the Section
+// 3.1 propagator pair; the Section 3.2 propagators with an advection
+// velocity that varies in space, eq. adVel):
+//   f(q)_field = sum_{m=-3..3} (wx[j][m] q(i+m, j) + wz[i][m] q(i, j+m))
+//              - acoustic centred differences + grad-div damping
+// (see stage.hip for the acoustic and damping terms).
 // ---------------------------------------------------------------------------
-struct Rk3Coef {
-  double wx[7], wz[7];   // advective weights at offsets -3..3
-  double cx2, cz2;       // c_s/(2 dx), c_s/(2 dz)
+struct StageCoef {
+  const double* wx;      // device, [nz][7]: x-weights of row j, offsets -3..3
+  const double* wz;      // device, [nx][7]: z-weights of column i
+  double ax1, ax2;       // acoustic x-difference ax1 d1x + ax2 d2x (times c_s)
+  double az1, az2;       // acoustic z-difference
+  double kxx, kxzu, kzz, kxzw;  // damping weights as in FineCoef (0 = none)
 };
 
 // out = base + beta * f(in) over ns states (each array with its own state
-// stride), one point per thread, neighbours read from global memory.
-hipError_t launch_rk3_stage(const double* in, int64_t in_stride,
-                            const double* base, int64_t base_stride,
-                            double* out, int64_t out_stride, int nx, int nz,
-                            int nstates, const Rk3Coef& c, double beta,
-                            hipStream_t s);
+// stride), or out = beta * f(in) when base is NULL; one point per thread,
+// neighbours read from global memory.
+hipError_t launch_stage(const double* in, int64_t in_stride,
+                        const double* base, int64_t base_stride, double* out,
+                        int64_t out_stride, int nx, int nz, int nstates,
+                        const StageCoef& c, double beta, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Coarse propagator (Section 3.2: partially split forward Euler; the slow

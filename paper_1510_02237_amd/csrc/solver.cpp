@@ -89,6 +89,7 @@ extern "C" void pr_opts_default(pr_opts* o) {
   o->tile_nt = 0;
   o->tile_zc = 0;
   o->windows = 1;
+  o->fine_acoustic_order = 4;
 }
 
 // Validates the problem; fills n_f, n_g.  Shared with the server.
@@ -122,9 +123,12 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
     return fail("windows must be in [1, 2^20]");
   if (o->scheme != PR_SCHEME_SPLIT && o->scheme != PR_SCHEME_RK3)
     return fail("scheme must be PR_SCHEME_SPLIT or PR_SCHEME_RK3");
-  if (!std::isfinite(o->V)) return fail("V must be finite");
-  if (o->scheme == PR_SCHEME_SPLIT && o->V != 0.0)
-    return fail("V must be 0 with PR_SCHEME_SPLIT (advection along x)");
+  if (!std::isfinite(o->V) || !std::isfinite(o->gamma))
+    return fail("V and gamma must be finite");
+  if (o->scheme == PR_SCHEME_RK3 && o->gamma != 0.0)
+    return fail("gamma must be 0 with PR_SCHEME_RK3 (constant velocity)");
+  if (o->fine_acoustic_order != 2 && o->fine_acoustic_order != 4)
+    return fail("fine_acoustic_order must be 2 or 4");
   if (!(o->stop_tol >= 0) || !std::isfinite(o->stop_tol))
     return fail("stop_tol must be finite and >= 0");
   const double slice = g->T / ((double)o->windows * P);
@@ -176,36 +180,92 @@ static void make_coef(pr_ctx* c) {
   const int nch = (ns + kCoarseMaxSubPerLaunch - 1) / kCoarseMaxSubPerLaunch;
   c->coarse_chunks.assign(nch, ns / nch);
   for (int q = 0; q < ns % nch; ++q) c->coarse_chunks[q] += 1;
-  // Section 3.1 pair.  F: sixth-order centred flux differenced, point
-  // weights (-1, 9, -45, 0, 45, -9, 1)/(60 h) at offsets -3..3; G:
-  // first-order upwind, U (q_i - q_{i-1})/h for U >= 0, U (q_{i+1} - q_i)/h
-  // for U < 0.  Stored as weights of f = -advection.
+  // Stage-kernel weights, stored as weights of f = -advection at offsets
+  // -3..3 of each row (x) and each column (z).  The velocity of row j
+  // along x and of column i along z is U + gamma (z_j - Lz/2) and
+  // V - gamma (x_i - Lx/2) (eq. adVel with a constant part).
+  //  * Section 3.1 pair.  F: sixth-order centred flux differenced, point
+  //    weights (-1, 9, -45, 0, 45, -9, 1)/(60 h).  G: first-order upwind,
+  //    vel (q_i - q_{i-1})/h for vel >= 0, vel (q_{i+1} - q_i)/h for vel < 0.
+  //  * Split scheme.  F: the fifth-order upwind weights above, per row and
+  //    column; G: the first-order upwind slow tendency, no acoustics.
   c->rk3 = c->o.scheme == PR_SCHEME_RK3;
-  if (c->rk3) {
-    static const double c6[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
-    const double V = c->o.V;
-    for (int k = 0; k < 7; ++k) {
-      c->rf.wx[k] = -U * c6[k] / (60.0 * dx);
-      c->rf.wz[k] = -V * c6[k] / (60.0 * dz);
-      c->rg.wx[k] = c->rg.wz[k] = 0.0;
-    }
-    if (U >= 0) {
-      c->rg.wx[3] = -U / dx;
-      c->rg.wx[2] = U / dx;
+  const double V = c->o.V, gam = c->o.gamma;
+  c->tables_f = c->rk3 || V != 0.0 || gam != 0.0 || c->o.fine_acoustic_order == 2;
+  c->tables_g = !c->rk3 && (V != 0.0 || gam != 0.0);
+  c->h_tabs.clear();
+  c->sf = prh::StageCoef{};
+  c->sg = prh::StageCoef{};
+  if (!c->tables_f && !c->tables_g) return;
+  const int nx = c->g.nx, nz = c->g.nz;
+  c->h_tabs.assign((size_t)14 * (nx + nz), 0.0);
+  double* fwx = c->h_tabs.data();
+  double* fwz = fwx + 7 * (size_t)nz;
+  double* gwx = fwz + 7 * (size_t)nx;
+  double* gwz = gwx + 7 * (size_t)nz;
+  static const double c6[7] = {-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0};
+  auto fine_w = [&](double vel, double h, double* out) {
+    if (c->rk3) {
+      for (int k = 0; k < 7; ++k) out[k] = -vel * c6[k] / (60.0 * h);
     } else {
-      c->rg.wx[4] = -U / dx;
-      c->rg.wx[3] = U / dx;
+      const double* wv = vel >= 0 ? wpos : wneg;
+      const int k0 = vel >= 0 ? 0 : 1;  // offset -3 or -2 first
+      for (int k = 0; k < 6; ++k) out[k0 + k] = -vel * wv[k] / (60.0 * h);
     }
-    if (V >= 0) {
-      c->rg.wz[3] = -V / dz;
-      c->rg.wz[2] = V / dz;
+  };
+  auto up1_w = [&](double vel, double h, double* out) {
+    if (vel >= 0) {
+      out[3] = -vel / h;
+      out[2] = vel / h;
     } else {
-      c->rg.wz[4] = -V / dz;
-      c->rg.wz[3] = V / dz;
+      out[4] = -vel / h;
+      out[3] = vel / h;
     }
-    c->rf.cx2 = c->rg.cx2 = cs / (2.0 * dx);
-    c->rf.cz2 = c->rg.cz2 = cs / (2.0 * dz);
+  };
+  for (int j = 0; j < nz; ++j) {
+    const double vel = U + gam * ((j + 0.5) * dz - 0.5 * c->g.Lz);
+    fine_w(vel, dx, fwx + 7 * (size_t)j);
+    up1_w(vel, dx, gwx + 7 * (size_t)j);
   }
+  for (int i = 0; i < nx; ++i) {
+    const double vel = V - gam * ((i + 0.5) * dx - 0.5 * c->g.Lx);
+    fine_w(vel, dz, fwz + 7 * (size_t)i);
+    up1_w(vel, dz, gwz + 7 * (size_t)i);
+  }
+  if (c->rk3) {
+    c->sf.ax1 = c->sg.ax1 = cs / (2.0 * dx);
+    c->sf.az1 = c->sg.az1 = cs / (2.0 * dz);
+  } else {
+    if (c->o.fine_acoustic_order == 2) {
+      c->sf.ax1 = cs / (2.0 * dx);
+      c->sf.az1 = cs / (2.0 * dz);
+    } else {
+      c->sf.ax1 = 8.0 * cs / (12.0 * dx);
+      c->sf.ax2 = -cs / (12.0 * dx);
+      c->sf.az1 = 8.0 * cs / (12.0 * dz);
+      c->sf.az2 = -cs / (12.0 * dz);
+    }
+    c->sf.kxx = c->fc.kxx;
+    c->sf.kxzu = c->fc.kxzu;
+    c->sf.kzz = c->fc.kzz;
+    c->sf.kxzw = c->fc.kxzw;
+  }
+}
+
+// Copies the stage-kernel weights to the device (once, at create time, so
+// that no allocation happens inside a captured graph) and points the
+// coefficient blocks at them.
+static int upload_tables(pr_ctx* c) {
+  if (c->h_tabs.empty()) return PR_OK;
+  const size_t bytes = c->h_tabs.size() * sizeof(double);
+  HC(hipMalloc((void**)&c->tabs, bytes));
+  HC(hipMemcpy(c->tabs, c->h_tabs.data(), bytes, hipMemcpyHostToDevice));
+  const int nx = c->g.nx, nz = c->g.nz;
+  c->sf.wx = c->tabs;
+  c->sf.wz = c->sf.wx + 7 * (size_t)nz;
+  c->sg.wx = c->sf.wz + 7 * (size_t)nx;
+  c->sg.wz = c->sg.wx + 7 * (size_t)nz;
+  return PR_OK;
 }
 
 static void clear_graphs(pr_ctx* c) {
@@ -256,8 +316,9 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
     RC(dalloc(c, &c->DX, w, "work"));
     RC(dalloc(c, &c->Yb, w, "work"));
     // third scratch block of run_coarse: the stored slow tendency (split
-    // scheme with more than one substep chunk) or an RK-3 step (rk3)
-    if (c->coarse_chunks.size() > 1 || c->rk3)
+    // scheme with more than one substep chunk or with the slow tendency
+    // from the stage kernel) or an RK-3 step (rk3)
+    if (c->coarse_chunks.size() > 1 || c->rk3 || c->tables_g)
       RC(dalloc(c, &c->Rb, w, "work"));
     c->wcap = wcap;
     changed = true;
@@ -336,9 +397,12 @@ int prh::retarget(pr_ctx* c, double c_s, double U, double dt_f, double dt_g,
   c->n_f = nf;
   c->n_g = ng;
   make_coef(c);
+  if (!c->h_tabs.empty())
+    return set_error(c, PR_EINVAL, "retarget: only the split scheme with "
+                     "advection along x and fourth-order fine acoustics");
   clear_graphs(c);
   c->r = 0;
-  if ((c->coarse_chunks.size() > 1 || c->rk3) && !c->Rb && c->wcap > 0)
+  if (c->coarse_chunks.size() > 1 && !c->Rb && c->wcap > 0)
     RC(dalloc(c, &c->Rb, (size_t)c->wcap * c->ld, "work"));
   return PR_OK;
 }
@@ -404,7 +468,7 @@ static void tile_for(pr_ctx* c, int ns, int* nt, int* zc) {
 // every candidate on the context's own buffers (Q -> Qt); the choice only
 // changes the speed, never the result.
 int prh::autotune(pr_ctx* c, int ns) {
-  if (c->rk3 || (c->o.tile_nt && c->o.tile_zc)) return PR_OK;
+  if (c->tables_f || (c->o.tile_nt && c->o.tile_zc)) return PR_OK;
   {
     std::lock_guard<std::mutex> lk(g_tile_mu);
     if (g_tiles.count(TileKey{c->g.nx, c->g.nz, ns, c->sgn})) return PR_OK;
@@ -491,13 +555,13 @@ int prh::run_sweep(pr_ctx* c, const double* in, int64_t is, double* out,
       double* dst = to_out ? out : ping;
       const int64_t dst_s = to_out ? os : ps;
       const double dt = c->fc.dt;
-      if (c->rk3) {
-        HC(launch_rk3_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns,
-                            c->rf, dt / 3.0, c->stream));
-        HC(launch_rk3_stage(A, ps, src, sst, B, ps, c->g.nx, c->g.nz, ns,
-                            c->rf, 0.5 * dt, c->stream));
-        HC(launch_rk3_stage(B, ps, src, sst, dst, dst_s, c->g.nx, c->g.nz, ns,
-                            c->rf, dt, c->stream));
+      if (c->tables_f) {
+        HC(launch_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns, c->sf,
+                        dt / 3.0, c->stream));
+        HC(launch_stage(A, ps, src, sst, B, ps, c->g.nx, c->g.nz, ns, c->sf,
+                        0.5 * dt, c->stream));
+        HC(launch_stage(B, ps, src, sst, dst, dst_s, c->g.nx, c->g.nz, ns,
+                        c->sf, dt, c->stream));
       } else {
         HC(launch_fine_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns,
                              c->fc, dt / 3.0, c->sgn, c->stream));
@@ -546,12 +610,12 @@ int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
     const double* src = in;
     for (int st = 0; st < c->n_g; ++st) {
       double* dst = ((c->n_g - 1 - st) % 2 == 0) ? out : R;
-      HC(launch_rk3_stage(src, stride, src, stride, pa, stride, c->g.nx,
-                          c->g.nz, ns, c->rg, dt / 3.0, c->stream));
-      HC(launch_rk3_stage(pa, stride, src, stride, pb, stride, c->g.nx,
-                          c->g.nz, ns, c->rg, 0.5 * dt, c->stream));
-      HC(launch_rk3_stage(pb, stride, src, stride, dst, stride, c->g.nx,
-                          c->g.nz, ns, c->rg, dt, c->stream));
+      HC(launch_stage(src, stride, src, stride, pa, stride, c->g.nx, c->g.nz,
+                      ns, c->sg, dt / 3.0, c->stream));
+      HC(launch_stage(pa, stride, src, stride, pb, stride, c->g.nx, c->g.nz,
+                      ns, c->sg, 0.5 * dt, c->stream));
+      HC(launch_stage(pb, stride, src, stride, dst, stride, c->g.nx, c->g.nz,
+                      ns, c->sg, dt, c->stream));
       src = dst;
     }
     return PR_OK;
@@ -561,6 +625,12 @@ int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
   const double* src = in;
   int q = 0;
   for (int step = 0; step < c->n_g; ++step) {
+    // With a z-velocity or a rotation the frozen slow tendency comes from
+    // the stage kernel (first-order upwind weights per row and column) and
+    // every substep launch loads it.
+    if (c->tables_g)
+      HC(launch_stage(src, stride, nullptr, 0, R, stride, c->g.nx, c->g.nz, ns,
+                      c->sg, 1.0, c->stream));
     for (int ch = 0; ch < nch; ++ch, ++q) {
       double* dst = (q == total - 1) ? out : ((q % 2 == 0) ? pa : pb);
       CoarseLaunch L;
@@ -572,7 +642,9 @@ int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
       L.nz = c->g.nz;
       L.nstates = ns;
       L.nsub = c->coarse_chunks[ch];
-      L.flags = ch == 0 ? (kCoarseComputeR | (nch > 1 ? kCoarseStoreR : 0)) : 0;
+      L.flags = (ch == 0 && !c->tables_g)
+                    ? (kCoarseComputeR | (nch > 1 ? kCoarseStoreR : 0))
+                    : 0;
       L.c = c->cc;
       HC(launch_coarse(L, c->stream));
       src = dst;
@@ -979,7 +1051,10 @@ extern "C" int pr_create_ex(const pr_grid* g, double c_s, double U,
   double rf = 0, rg = 0;
   rc = pr_check_stability_impl(g, c_s, U, dt_f, dt_g, o, &rf, &rg);
   if (rc) return set_error(nullptr, rc, "stability scan failed");
-  if (rf > 1.0 + 1e-12 || rg > 1.0 + 1e-12)
+  // Enforced for a constant velocity only: with a rotation the radii are a
+  // frozen-coefficient estimate, which exceeds 1 for propagators that are
+  // stable on the rotating flow (the coarse-CFL-4 runs of Section 3.2).
+  if (o->gamma == 0.0 && (rf > 1.0 + 1e-12 || rg > 1.0 + 1e-12))
     return set_error(nullptr, PR_EUNSTABLE,
                      "unstable propagator: spectral radius fine %.15g, coarse %.15g",
                      rf, rg);
@@ -997,7 +1072,7 @@ extern "C" int pr_create_ex(const pr_grid* g, double c_s, double U,
   c->d = 3 * c->n;
   c->ld = (c->d + 63) / 64 * 64;
   make_coef(c);
-  if (c->rk3) c->o.form = PR_FORM_STAGEWISE;  // only stage kernels
+  if (c->tables_f) c->o.form = PR_FORM_STAGEWISE;  // only stage kernels
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) {
     if (hip_stream) {
@@ -1016,6 +1091,12 @@ extern "C" int pr_create_ex(const pr_grid* g, double c_s, double U,
     pr_destroy(c);
     return PR_EDEVICE;
   }
+  if (upload_tables(c) != PR_OK) {
+    const int rc = c->tabs ? PR_EDEVICE : PR_ENOMEM;
+    set_error(nullptr, rc, "stage weights: %s", c->err.c_str());
+    pr_destroy(c);
+    return rc;
+  }
   *out = c;
   return PR_OK;
 }
@@ -1033,6 +1114,7 @@ extern "C" void pr_destroy(pr_ctx* c) {
                     c->S, c->D, c->small, c->ext_ping, c->ext_io};
   for (double* p : bufs)
     if (p) (void)hipFree(p);
+  if (c->tabs) (void)hipFree(c->tabs);
   if (c->ism) (void)hipFree(c->ism);
   if (c->h_ism) (void)hipHostFree(c->h_ism);
   if (c->nrm) (void)hipFree(c->nrm);
@@ -1051,8 +1133,9 @@ extern "C" int pr_set_form(pr_ctx* c, int32_t form) {
   if (!c) return PR_EINVAL;
   if (form < 0 || form > PR_FORM_STAGEWISE)
     return set_error(c, PR_EINVAL, "unknown form %d", form);
-  // The Section 3.1 pair has only the stage kernels.
-  c->o.form = c->rk3 ? PR_FORM_STAGEWISE : form;
+  // Right-hand sides with per-row or per-column weights have only the
+  // stage kernels.
+  c->o.form = c->tables_f ? PR_FORM_STAGEWISE : form;
   return PR_OK;
 }
 

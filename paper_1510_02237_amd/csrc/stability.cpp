@@ -199,28 +199,39 @@ void scan_rk3(int nx, int nz, double dx, double dz, double c_s, double U,
 
 }  // namespace
 
-int pr_check_stability_impl(const pr_grid* g, double c_s, double U,
-                            double dt_f, double dt_g, const pr_opts* o,
-                            double* rho_f, double* rho_g) {
-  const int nx = g->nx, nz = g->nz;
-  if (o->scheme == PR_SCHEME_RK3) {
-    const bool all = (long long)nx * nz <= 65536;
-    scan_rk3(nx, nz, g->Lx / nx, g->Lz / nz, c_s, U, o->V, dt_f, dt_g,
-             all || nx <= 256 ? nx : 256, all || nz <= 256 ? nz : 256, rho_f,
-             rho_g);
-    return PR_OK;
-  }
-  const double dx = g->Lx / nx, dz = g->Lz / nz;
+namespace {
+
+// Fifth-order upwind derivative symbol (point weights /(60 h) at offsets
+// -3..2 for vel >= 0, mirrored for vel < 0) times -vel.
+cd adv5_symbol(double t, double h, double vel) {
+  static const double wpos[6] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0};
+  static const double wneg[6] = {3.0, -30.0, -20.0, 60.0, -15.0, 2.0};
+  const double* w = vel >= 0 ? wpos : wneg;
+  const int m0 = vel >= 0 ? -3 : -2;
+  const cd I(0.0, 1.0);
+  cd a = 0.0;
+  for (int k = 0; k < 6; ++k) a += w[k] * std::exp(I * (double)(m0 + k) * t);
+  return -vel * a / (60.0 * h);
+}
+
+// First-order upwind derivative symbol times -vel.
+cd adv1_symbol(double t, double h, double vel) {
+  const cd I(0.0, 1.0);
+  return vel >= 0 ? -vel * (1.0 - std::exp(-I * t)) / h
+                  : -vel * (std::exp(I * t) - 1.0) / h;
+}
+
+// Scan of the Section 3.2 pair for the constant velocity (U, V): F is RK-3
+// of fifth-order upwind advection, centred acoustics of order `order` and
+// grad-div damping; G is N_sound forward-backward substeps with the frozen
+// first-order upwind slow tendency.
+void scan_split(int nx, int nz, double dx, double dz, double c_s, double U,
+                double V, double dt_f, double dt_g, const pr_opts* o,
+                int kxn, int kzn, double* rho_f, double* rho_g) {
   const double ax_f = o->nu_f * dx * dx / dt_f, az_f = o->nu_f * dz * dz / dt_f;
   const double dtau = dt_g / o->n_sound;
   const double ax_c = o->nu_c * dx * dx / dtau, az_c = o->nu_c * dz * dz / dtau;
-  static const double wpos[6] = {-2.0, 15.0, -60.0, 20.0, 30.0, -3.0};
-  static const double wneg[6] = {3.0, -30.0, -20.0, 60.0, -15.0, 2.0};
-  const double* w = U >= 0 ? wpos : wneg;
-  const int m0 = U >= 0 ? -3 : -2;
-  const bool all = (long long)nx * nz <= 65536;
-  const int kxn = all || nx <= 256 ? nx : 256;
-  const int kzn = all || nz <= 256 ? nz : 256;
+  const bool fourth = o->fine_acoustic_order != 2;
   const double two_pi = 2.0 * M_PI;
   const cd I(0.0, 1.0);
   double rf = 0.0, rg = 0.0;
@@ -230,37 +241,26 @@ int pr_check_stability_impl(const pr_grid* g, double c_s, double U,
     for (int b = 0; b < kzn; ++b) {
       const long long kz = kzn == nz ? b : (long long)b * nz / 256;
       const double tz = two_pi * (double)kz / nz;
-      cd a5 = 0.0;
-      for (int k = 0; k < 6; ++k) a5 += w[k] * std::exp(I * (double)(m0 + k) * tx);
-      a5 *= -U / (60.0 * dx);
-      const cd dx4 = I * (8.0 * std::sin(tx) - std::sin(2.0 * tx)) / (6.0 * dx);
-      const cd dz4 = I * (8.0 * std::sin(tz) - std::sin(2.0 * tz)) / (6.0 * dz);
+      const cd a5 = adv5_symbol(tx, dx, U) + adv5_symbol(tz, dz, V);
+      const cd dx2 = I * std::sin(tx) / dx, dz2 = I * std::sin(tz) / dz;
+      const cd dxf = fourth ? I * (8.0 * std::sin(tx) - std::sin(2.0 * tx)) / (6.0 * dx) : dx2;
+      const cd dzf = fourth ? I * (8.0 * std::sin(tz) - std::sin(2.0 * tz)) / (6.0 * dz) : dz2;
       const double gxx = -4.0 * std::pow(std::sin(0.5 * tx), 2) / (dx * dx);
       const double gzz = -4.0 * std::pow(std::sin(0.5 * tz), 2) / (dz * dz);
       const double gxz = -std::sin(tx) * std::sin(tz) / (dx * dz);
       M3 Z;
       Z.a[0][0] = a5 + ax_f * gxx;
       Z.a[0][1] = ax_f * gxz;
-      Z.a[0][2] = -c_s * dx4;
+      Z.a[0][2] = -c_s * dxf;
       Z.a[1][0] = az_f * gxz;
       Z.a[1][1] = a5 + az_f * gzz;
-      Z.a[1][2] = -c_s * dz4;
-      Z.a[2][0] = -c_s * dx4;
-      Z.a[2][1] = -c_s * dz4;
+      Z.a[1][2] = -c_s * dzf;
+      Z.a[2][0] = -c_s * dxf;
+      Z.a[2][1] = -c_s * dzf;
       Z.a[2][2] = a5;
-      for (auto& row : Z.a)
-        for (auto& v : row) v *= dt_f;
-      const M3 Z2 = mul(Z, Z), Z3 = mul(Z2, Z);
-      M3 R;
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          R.a[i][j] = (i == j ? 1.0 : 0.0) + Z.a[i][j] + 0.5 * Z2.a[i][j] +
-                      Z3.a[i][j] / 6.0;
-      rf = std::max(rf, spectral_radius(R));
+      rf = std::max(rf, spectral_radius(rk3_amplification(Z, dt_f)));
       // coarse step
-      const cd a1 = U >= 0 ? -U * (1.0 - std::exp(-I * tx)) / dx
-                           : -U * (std::exp(I * tx) - 1.0) / dx;
-      const cd dx2 = I * std::sin(tx) / dx, dz2 = I * std::sin(tz) / dz;
+      const cd a1 = adv1_symbol(tx, dx, U) + adv1_symbol(tz, dz, V);
       M3 Y;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Y.a[i][j] = i == j ? 1.0 : 0.0;
@@ -285,6 +285,43 @@ int pr_check_stability_impl(const pr_grid* g, double c_s, double U,
       rg = std::max(rg, spectral_radius(Y));
     }
   }
+  *rho_f = rf;
+  *rho_g = rg;
+}
+
+}  // namespace
+
+int pr_check_stability_impl(const pr_grid* g, double c_s, double U,
+                            double dt_f, double dt_g, const pr_opts* o,
+                            double* rho_f, double* rho_g) {
+  const int nx = g->nx, nz = g->nz;
+  const bool all = (long long)nx * nz <= 65536;
+  const int kxn = all || nx <= 256 ? nx : 256;
+  const int kzn = all || nz <= 256 ? nz : 256;
+  const double dx = g->Lx / nx, dz = g->Lz / nz;
+  if (o->scheme == PR_SCHEME_RK3) {
+    scan_rk3(nx, nz, dx, dz, c_s, U, o->V, dt_f, dt_g, kxn, kzn, rho_f, rho_g);
+    return PR_OK;
+  }
+  if (o->gamma == 0.0) {
+    scan_split(nx, nz, dx, dz, c_s, U, o->V, dt_f, dt_g, o, kxn, kzn, rho_f,
+               rho_g);
+    return PR_OK;
+  }
+  // Frozen coefficients at the extreme velocities of the rows (x) and of
+  // the columns (z): U + gamma (z_j - Lz/2) and V - gamma (x_i - Lx/2).
+  const double zlo = 0.5 * dz - 0.5 * g->Lz, zhi = (nz - 0.5) * dz - 0.5 * g->Lz;
+  const double xlo = 0.5 * dx - 0.5 * g->Lx, xhi = (nx - 0.5) * dx - 0.5 * g->Lx;
+  const double us[2] = {U + o->gamma * zlo, U + o->gamma * zhi};
+  const double vs[2] = {o->V - o->gamma * xlo, o->V - o->gamma * xhi};
+  double rf = 0.0, rg = 0.0;
+  for (double u : us)
+    for (double v : vs) {
+      double f, gg;
+      scan_split(nx, nz, dx, dz, c_s, u, v, dt_f, dt_g, o, kxn, kzn, &f, &gg);
+      rf = std::max(rf, f);
+      rg = std::max(rg, gg);
+    }
   *rho_f = rf;
   *rho_g = rg;
   return PR_OK;

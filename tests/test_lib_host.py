@@ -128,6 +128,66 @@ def test_demo_pair_is_stable(lib):
     assert rf <= 1 + 1e-12 and rg <= 1 + 1e-12
 
 
+@pytest.mark.parametrize("U,V,order", [(0.1, -0.07, 4), (-0.2, 0.15, 2),
+                                       (0.0, 0.2, 4)])
+def test_stability_scan_split_with_z_velocity(lib, U, V, order):
+    """Split pair with a constant (U, V) and either acoustic order: the
+    scan against numpy eigenvalues of the amplification matrices written
+    from the stencil weights."""
+    from test_oracle_rotation import fine_symbol_uv, coarse_symbol_uv
+    prm = Params(nx=16, nz=12, c_s=1.0, U=U, V=V, dt_f=0.2 / 16,
+                 dt_g=2.0 / 16, P=1, T=2.0 / 16, fine_acoustic_order=order)
+    want_f = want_g = 0.0
+    for kx in range(prm.nx):
+        for kz in range(prm.nz):
+            want_f = max(want_f, np.abs(np.linalg.eigvals(
+                rk3_poly(prm.dt_f * fine_symbol_uv(prm, kx, kz)))).max())
+            want_g = max(want_g, np.abs(np.linalg.eigvals(
+                coarse_symbol_uv(prm, kx, kz))).max())
+    got_f, got_g = binding.check_stability(16, 12, 1.0, U, prm.dt_f, prm.dt_g,
+                                           V=V, fine_acoustic_order=order)
+    assert abs(got_f - want_f) < 1e-12 and abs(got_g - want_g) < 1e-12
+
+
+def test_stability_scan_rotation_is_frozen_at_extreme_velocities(lib):
+    """With gamma != 0 the scan reports the largest radii of the symbols
+    frozen at the four extreme (x-velocity of a row, z-velocity of a
+    column) pairs."""
+    from oracle import operators as ops
+    from test_oracle_rotation import fine_symbol_uv, coarse_symbol_uv
+    base = dict(nx=16, nz=16, c_s=3.0, U=0.1, V=-0.2, dt_f=0.2 / 48,
+                dt_g=2.0 / 48, P=1, T=2.0 / 48, fine_acoustic_order=2)
+    rot = Params(**base, gamma=2.0)
+    ux, vz = ops.velocity_x(rot)[:, 0], ops.velocity_z(rot)[0]
+    want_f = want_g = 0.0
+    for u in (ux.min(), ux.max()):
+        for v in (vz.min(), vz.max()):
+            p = Params(**{**base, "U": u, "V": v})
+            for kx in range(16):
+                for kz in range(16):
+                    want_f = max(want_f, np.abs(np.linalg.eigvals(
+                        rk3_poly(p.dt_f * fine_symbol_uv(p, kx, kz)))).max())
+                    want_g = max(want_g, np.abs(np.linalg.eigvals(
+                        coarse_symbol_uv(p, kx, kz))).max())
+    got_f, got_g = binding.check_stability(16, 16, 3.0, 0.1, rot.dt_f,
+                                           rot.dt_g, V=-0.2, gamma=2.0,
+                                           fine_acoustic_order=2)
+    assert abs(got_f - want_f) < 1e-12 and abs(got_g - want_g) < 1e-12
+
+
+def test_rotation_frozen_estimate_exceeds_one_at_coarse_cfl_4(lib):
+    """The frozen-coefficient estimate of the paper's coarse-CFL-4 run
+    exceeds 1, but the propagator does not grow on the rotating flow (the
+    oracle's pins), which is why pr_create does not enforce it when gamma
+    is set (the GPU tests create this context)."""
+    prob = W.rotation_problem(40, 6, 4.0)
+    _, rg = binding.check_stability(
+        40, 40, prob["c_s"], 0.0, prob["dt_f"], prob["dt_g"],
+        gamma=prob["gamma"], fine_acoustic_order=2, n_sound=4,
+        windows=prob["windows"])
+    assert rg > 1.04
+
+
 def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     h = ctypes.c_void_p()
     o = binding.default_opts(**opts)
@@ -149,7 +209,9 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(windows=0), "windows"),
     (dict(windows=3), "(T/(windows*P))/dt_f"),
     (dict(scheme=7), "scheme"),
-    (dict(V=0.1), "V must be 0"),
+    (dict(scheme=1, gamma=1.0), "gamma must be 0"),
+    (dict(gamma=float("nan")), "V and gamma must be finite"),
+    (dict(fine_acoustic_order=3), "fine_acoustic_order"),
     (dict(stop_tol=-1.0), "stop_tol"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
@@ -157,7 +219,9 @@ def test_create_rejects_bad_arguments(lib, kw, why):
                 P=8)
     opts = {k: kw.pop(k) for k in list(kw) if k in ("n_sound", "tile_nt",
                                                    "tile_zc", "windows",
-                                                   "scheme", "V", "stop_tol")}
+                                                   "scheme", "V", "stop_tol",
+                                                   "gamma",
+                                                   "fine_acoustic_order")}
     args.update(kw)
     rc, h = _create(lib, **args, **opts)
     assert rc == binding.PR_EINVAL and not h.value
