@@ -257,6 +257,7 @@ def main():
         del ser
         res["windows"] = windows_leg(dev, max(1, args.steps // 2))
         res["instability"] = instability_leg()
+        res["paper_tables"] = paper_tables_leg(dev)
         if args.serve > 0:
             res["served"] = serve_leg(args.serve, args.serve_rate)
     if not args.no_cpu:
@@ -327,6 +328,72 @@ def instability_leg():
                 U=prob["U"], V=prob["V"], c_s=prob["c_s"],
                 max_abs_q_per_window=traj, ms=times,
                 eps_kse=_rel_l2(qk, ref), eps_parareal=_rel_l2(qp, ref))
+
+
+PAPER_TABLES = os.path.join(ROOT, "tests", "golden", "paper_tables_1_2.json")
+
+
+def paper_tables_leg(dev):
+    """The solid-body-rotation runs of Section 3.2 on 40 x 40 cells: every
+    cell (coarse CFL, P, K) of Tables 1 and 2 run to T = 2 (one coarse step
+    per slice, T / (P dt_g) windows), with its time to solution on the GPU,
+    the serial fine run's time, the error (eq. errorDef) and the paper's
+    printed error and speedup beside it.  Plus the error after every tenth
+    window for P = 6 (the data of the paper's error-versus-time figure),
+    from chained one-window solves."""
+    import torch
+    from paper_1510_02237_amd import binding, workloads as W
+    paper = {(c["cfl_c"], c["P"], c["K"]): c
+             for c in json.load(open(PAPER_TABLES))["cells"]}
+    u0 = torch.from_numpy(W.ic_cosine_bell(40, 40, centre=(0.5, 0.65))).to(dev)
+    cells, ref, ser_ms = [], None, None
+    for cc, P, K in W.PAPER_TABLE_CELLS:
+        ctx = binding.Context.from_problem(W.rotation_problem(40, P, cc))
+        if ref is None:
+            ref = ctx.serial_fine(u0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.serial_fine(u0, out=ref)
+            torch.cuda.synchronize()
+            ser_ms = (time.perf_counter() - t0) * 1e3
+            refh = ref.cpu().numpy()
+        out = ctx.solve(u0, K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.solve(u0, K, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        pp = paper[(cc, P, K)]
+        cells.append(dict(cfl_c=cc, P=P, K=K, windows=ctx.opts.windows, ms=ms,
+                          speedup_vs_serial_fine=ser_ms / ms,
+                          eps=_rel_l2(out.cpu().numpy(), refh),
+                          paper_eps=pp["eps"], paper_speedup=pp["speedup"]))
+    def energy(q):
+        # total energy of Section 3.2.3: integral of u^2 + w^2 + p^2
+        return float((q * q).sum()) / (40 * 40)
+
+    traj, etraj = {}, {}
+    for cc in (2.0, 4.0):
+        prob = W.rotation_problem(40, 6, cc)
+        M = prob["windows"]
+        one = binding.Context.from_problem(
+            dict(prob, windows=1, T=prob["T"] / M))
+        for K in (1, 2, 3):
+            qf, qk, e, en, enf = u0, u0, [], [], []
+            for w in range(M):
+                qf = one.serial_fine(qf)
+                qk = one.solve(qk, K)
+                if (w + 1) % 10 == 0:
+                    e.append(_rel_l2(qk.cpu().numpy(), qf.cpu().numpy()))
+                    en.append(energy(qk))
+                    enf.append(energy(qf))
+            traj[f"cfl_c={cc:g} K={K}"] = e
+            etraj[f"cfl_c={cc:g} K={K}"] = en
+        etraj[f"cfl_c={cc:g} serial fine"] = enf
+    return dict(workload="rotation 40x40, T = 2 (Section 3.2)",
+                serial_fine_ms=ser_ms, cells=cells,
+                eps_every_10_windows_P6=traj,
+                energy_every_10_windows_P6=dict(initial=energy(u0), **etraj))
 
 
 def windows_leg(dev, steps):
