@@ -155,6 +155,14 @@ typedef struct pr_opts {
                              per-column advective weights) and the slow
                              tendency of G comes from a separate launch;
                              the server accepts none of these.               */
+  int32_t coarse_order;   /* order of the upwind slow tendency of G in
+                             PR_SCHEME_SPLIT: 1 (default, the main runs of
+                             Section 3.2) or 3 (its less diffusive G; the
+                             slow tendency then comes from the stage kernel).
+                             Forward Euler on the frozen third-order tendency
+                             grows on long waves, so with a constant velocity
+                             pr_create returns PR_EUNSTABLE.  The server
+                             accepts only 1.                                   */
 } pr_opts;
 
 typedef struct pr_ctx pr_ctx;

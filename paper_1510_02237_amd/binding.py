@@ -46,7 +46,8 @@ class Opts(ctypes.Structure):
                 ("windows", ctypes.c_int32), ("scheme", ctypes.c_int32),
                 ("V", ctypes.c_double), ("stop_tol", ctypes.c_double),
                 ("gamma", ctypes.c_double),
-                ("fine_acoustic_order", ctypes.c_int32)]
+                ("fine_acoustic_order", ctypes.c_int32),
+                ("coarse_order", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -235,7 +236,8 @@ class Context:
                  windows=prob.get("windows", 1),
                  scheme=prob.get("scheme", "split"), V=prob.get("V", 0.0),
                  gamma=prob.get("gamma", 0.0),
-                 fine_acoustic_order=prob.get("fine_acoustic_order", 4))
+                 fine_acoustic_order=prob.get("fine_acoustic_order", 4),
+                 coarse_order=prob.get("coarse_order", 1))
         o.update(opts)
         return cls(prob["nx"], prob["nz"], prob["c_s"], prob["U"],
                    prob["dt_f"], prob["dt_g"], prob["P"], T=prob["T"], **o)

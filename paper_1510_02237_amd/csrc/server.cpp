@@ -512,10 +512,12 @@ extern "C" int pr_submit_ex(pr_server* s, const pr_grid* g, double c_s,
     return set_serr(s, PR_EINVAL, "the server runs the split scheme only");
   if (o->stop_tol != 0.0)
     return set_serr(s, PR_EINVAL, "the server runs a fixed K (stop_tol = 0)");
-  if (o->V != 0.0 || o->gamma != 0.0 || o->fine_acoustic_order != 4)
+  if (o->V != 0.0 || o->gamma != 0.0 || o->fine_acoustic_order != 4 ||
+      o->coarse_order != 1)
     return set_serr(s, PR_EINVAL, "the server advects along x with "
-                    "fourth-order fine acoustics (V = gamma = 0, "
-                    "fine_acoustic_order = 4)");
+                    "fourth-order fine acoustics and a first-order coarse "
+                    "slow tendency (V = gamma = 0, fine_acoustic_order = 4, "
+                    "coarse_order = 1)");
   int nf, ng;
   std::string msg;
   int rc = pr_validate(g, c_s, U, dt_f, dt_g, P, o, &nf, &ng, &msg);

@@ -90,6 +90,7 @@ extern "C" void pr_opts_default(pr_opts* o) {
   o->tile_zc = 0;
   o->windows = 1;
   o->fine_acoustic_order = 4;
+  o->coarse_order = 1;
 }
 
 // Validates the problem; fills n_f, n_g.  Shared with the server.
@@ -129,6 +130,10 @@ int pr_validate(const pr_grid* g, double c_s, double U, double dt_f,
     return fail("gamma must be 0 with PR_SCHEME_RK3 (constant velocity)");
   if (o->fine_acoustic_order != 2 && o->fine_acoustic_order != 4)
     return fail("fine_acoustic_order must be 2 or 4");
+  if (o->coarse_order != 1 && o->coarse_order != 3)
+    return fail("coarse_order must be 1 or 3");
+  if (o->scheme == PR_SCHEME_RK3 && o->coarse_order != 1)
+    return fail("coarse_order must be 1 with PR_SCHEME_RK3");
   if (!(o->stop_tol >= 0) || !std::isfinite(o->stop_tol))
     return fail("stop_tol must be finite and >= 0");
   const double slice = g->T / ((double)o->windows * P);
@@ -188,11 +193,14 @@ static void make_coef(pr_ctx* c) {
   //    weights (-1, 9, -45, 0, 45, -9, 1)/(60 h).  G: first-order upwind,
   //    vel (q_i - q_{i-1})/h for vel >= 0, vel (q_{i+1} - q_i)/h for vel < 0.
   //  * Split scheme.  F: the fifth-order upwind weights above, per row and
-  //    column; G: the first-order upwind slow tendency, no acoustics.
+  //    column; G: the first-order (or third-order) upwind slow tendency, no
+  //    acoustics.  Third order: the Wicker-Skamarock flux of order 3
+  //    differenced, point weights (1, -6, 3, 2)/(6 h) at offsets -2..1 for
+  //    vel >= 0, (-2, -3, 6, -1)/(6 h) at -1..2 for vel < 0.
   c->rk3 = c->o.scheme == PR_SCHEME_RK3;
   const double V = c->o.V, gam = c->o.gamma;
   c->tables_f = c->rk3 || V != 0.0 || gam != 0.0 || c->o.fine_acoustic_order == 2;
-  c->tables_g = !c->rk3 && (V != 0.0 || gam != 0.0);
+  c->tables_g = !c->rk3 && (V != 0.0 || gam != 0.0 || c->o.coarse_order == 3);
   c->h_tabs.clear();
   c->sf = prh::StageCoef{};
   c->sg = prh::StageCoef{};
@@ -213,8 +221,15 @@ static void make_coef(pr_ctx* c) {
       for (int k = 0; k < 6; ++k) out[k0 + k] = -vel * wv[k] / (60.0 * h);
     }
   };
+  static const double u3pos[4] = {1.0, -6.0, 3.0, 2.0};
+  static const double u3neg[4] = {-2.0, -3.0, 6.0, -1.0};
+  const bool third = !c->rk3 && c->o.coarse_order == 3;
   auto up1_w = [&](double vel, double h, double* out) {
-    if (vel >= 0) {
+    if (third) {
+      const double* wv = vel >= 0 ? u3pos : u3neg;
+      const int k0 = vel >= 0 ? 1 : 2;  // offset -2 or -1 first
+      for (int k = 0; k < 4; ++k) out[k0 + k] = -vel * wv[k] / (6.0 * h);
+    } else if (vel >= 0) {
       out[3] = -vel / h;
       out[2] = vel / h;
     } else {
@@ -399,7 +414,8 @@ int prh::retarget(pr_ctx* c, double c_s, double U, double dt_f, double dt_g,
   make_coef(c);
   if (!c->h_tabs.empty())
     return set_error(c, PR_EINVAL, "retarget: only the split scheme with "
-                     "advection along x and fourth-order fine acoustics");
+                     "advection along x, fourth-order fine acoustics and a "
+                     "first-order coarse slow tendency");
   clear_graphs(c);
   c->r = 0;
   if (c->coarse_chunks.size() > 1 && !c->Rb && c->wcap > 0)

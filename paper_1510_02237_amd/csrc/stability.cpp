@@ -214,17 +214,25 @@ cd adv5_symbol(double t, double h, double vel) {
   return -vel * a / (60.0 * h);
 }
 
-// First-order upwind derivative symbol times -vel.
-cd adv1_symbol(double t, double h, double vel) {
+// First-order (or, with order 3, third-order) upwind derivative symbol
+// times -vel; third order has point weights (1, -6, 3, 2)/6 at offsets
+// -2..1 for vel >= 0, mirrored for vel < 0.
+cd adv1_symbol(double t, double h, double vel, int order = 1) {
   const cd I(0.0, 1.0);
+  if (order == 3) {
+    auto e = [&](int m) { return std::exp(I * (double)m * t); };
+    const cd a = vel >= 0 ? e(-2) - 6.0 * e(-1) + 3.0 + 2.0 * e(1)
+                          : -2.0 * e(-1) - 3.0 + 6.0 * e(1) - e(2);
+    return -vel * a / (6.0 * h);
+  }
   return vel >= 0 ? -vel * (1.0 - std::exp(-I * t)) / h
                   : -vel * (std::exp(I * t) - 1.0) / h;
 }
 
 // Scan of the Section 3.2 pair for the constant velocity (U, V): F is RK-3
-// of fifth-order upwind advection, centred acoustics of order `order` and
+// of fifth-order upwind advection, centred acoustics of the fine order and
 // grad-div damping; G is N_sound forward-backward substeps with the frozen
-// first-order upwind slow tendency.
+// upwind slow tendency of the coarse order.
 void scan_split(int nx, int nz, double dx, double dz, double c_s, double U,
                 double V, double dt_f, double dt_g, const pr_opts* o,
                 int kxn, int kzn, double* rho_f, double* rho_g) {
@@ -260,7 +268,8 @@ void scan_split(int nx, int nz, double dx, double dz, double c_s, double U,
       Z.a[2][2] = a5;
       rf = std::max(rf, spectral_radius(rk3_amplification(Z, dt_f)));
       // coarse step
-      const cd a1 = adv1_symbol(tx, dx, U) + adv1_symbol(tz, dz, V);
+      const cd a1 = adv1_symbol(tx, dx, U, o->coarse_order) +
+                    adv1_symbol(tz, dz, V, o->coarse_order);
       M3 Y;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Y.a[i][j] = i == j ? 1.0 : 0.0;

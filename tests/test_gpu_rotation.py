@@ -48,8 +48,13 @@ def uv_problem(nx, nz, U, V, order, n_sound, P=2):
 def _cases():
     rot40 = short(W.rotation_problem(40, 6, 4.0), 1)
     rot80 = short(W.rotation_problem(80, 6, 2.0), 1)
+    # the less diffusive G of the energy runs (Section 3.2): third-order
+    # slow tendency, nu_c = 0.005, N_sound = 8 (two substep launches), no
+    # fine damping
+    rot40_o3 = short(W.rotation_problem(40, 6, 2.0), 1)
+    rot40_o3.update(coarse_order=3, nu_c=0.005, nu_f=0.0, n_sound=8)
     return [("rot40_cc4", rot40), ("rot80_cc2", rot80),
-            ("rot40_ns6", dict(rot40, n_sound=6)),
+            ("rot40_ns6", dict(rot40, n_sound=6)), ("rot40_o3", rot40_o3),
             ("uv_48x24_o4", uv_problem(48, 24, 0.1, -0.07, 4, 4)),
             ("uv_40x24_o2_ns6", uv_problem(40, 24, -0.2, 0.15, 2, 6))]
 
@@ -85,6 +90,21 @@ def test_batched_coarse_matches_single():
     for s in (0, 5):
         got = ctx.coarse_step(Q[s], use_krylov=True)
         assert rel_l2(got, FQ[s]) <= 1e-10, s
+
+
+def test_less_diffusive_G_windowed_solve_matches_oracle():
+    """Two windows of the energy-run configuration with the third-order
+    coarse slow tendency (Section 3.2) on the GPU against the oracle."""
+    prob = short(W.rotation_problem(40, 6, 2.0), 2)
+    prob.update(coarse_order=3, nu_c=0.005, nu_f=0.0, n_sound=8)
+    prm = Params(**prob)
+    u0 = W.ic_cosine_bell(40, 40, centre=(0.5, 0.65))
+    say("rotation less diffusive G solve")
+    ctx = binding.Context.from_problem(prob)
+    got = ctx.solve(u0, 2)
+    want = oracle.kse_parareal(u0, prm, K=2)
+    assert rel_l2(got, want["q"][prm.P]) <= 1e-10
+    assert ctx.stats()["rank"] == want["window_ranks"][-1]
 
 
 @pytest.fixture(scope="module")
@@ -162,7 +182,8 @@ def test_server_rejects_rotation():
         prob = W.problem(64, 32, 8)
         u0 = np.zeros((3, 32, 64))
         t = ctypes.c_uint64()
-        for kw in (dict(gamma=1.0), dict(V=0.1), dict(fine_acoustic_order=2)):
+        for kw in (dict(gamma=1.0), dict(V=0.1), dict(fine_acoustic_order=2),
+                   dict(coarse_order=3)):
             o = binding.default_opts(**kw)
             rc = lib.pr_submit_ex(
                 srv, ctypes.byref(binding.grid(64, 32)), 1.0, 0.1,

@@ -188,6 +188,30 @@ def test_rotation_frozen_estimate_exceeds_one_at_coarse_cfl_4(lib):
     assert rg > 1.04
 
 
+@pytest.mark.parametrize("U", [0.1, -0.2])
+def test_stability_scan_third_order_coarse(lib, U):
+    """The less diffusive G of Section 3.2 (third-order slow tendency,
+    nu_c = 0.005, N_sound = 8): the scan against numpy eigenvalues of the
+    substep product written from the stencil weights; it exceeds 1."""
+    from test_oracle_operators import _symbols
+    from test_oracle_propagators import _a3, _coarse_step_from
+    prm = Params(nx=16, nz=12, c_s=1.0, U=U, dt_f=0.2 / 16, dt_g=2.0 / 16,
+                 P=1, T=2.0 / 16, n_sound=8, nu_f=0.0, nu_c=0.005,
+                 coarse_order=3)
+    want = 0.0
+    for kx in range(prm.nx):
+        for kz in range(prm.nz):
+            s = _symbols(2 * np.pi * kx / prm.nx, 2 * np.pi * kz / prm.nz,
+                         prm.dx, prm.dz, prm.U)
+            s["a1"] = _a3(2 * np.pi * kx / prm.nx, prm.dx, prm.U)
+            want = max(want, np.abs(np.linalg.eigvals(
+                _coarse_step_from(prm, s))).max())
+    _, got = binding.check_stability(16, 12, 1.0, U, prm.dt_f, prm.dt_g,
+                                     n_sound=8, nu_f=0.0, nu_c=0.005,
+                                     coarse_order=3)
+    assert abs(got - want) < 1e-12 and got > 1.0
+
+
 def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     h = ctypes.c_void_p()
     o = binding.default_opts(**opts)
@@ -212,6 +236,8 @@ def _create(lib, nx, nz, c_s, U, dt_f, dt_g, P, T=1.0, **opts):
     (dict(scheme=1, gamma=1.0), "gamma must be 0"),
     (dict(gamma=float("nan")), "V and gamma must be finite"),
     (dict(fine_acoustic_order=3), "fine_acoustic_order"),
+    (dict(coarse_order=2), "coarse_order must be 1 or 3"),
+    (dict(scheme=1, coarse_order=3), "coarse_order must be 1 with"),
     (dict(stop_tol=-1.0), "stop_tol"),
 ])
 def test_create_rejects_bad_arguments(lib, kw, why):
@@ -221,7 +247,8 @@ def test_create_rejects_bad_arguments(lib, kw, why):
                                                    "tile_zc", "windows",
                                                    "scheme", "V", "stop_tol",
                                                    "gamma",
-                                                   "fine_acoustic_order")}
+                                                   "fine_acoustic_order",
+                                                   "coarse_order")}
     args.update(kw)
     rc, h = _create(lib, **args, **opts)
     assert rc == binding.PR_EINVAL and not h.value
@@ -232,6 +259,11 @@ def test_create_rejects_unstable_coarse(lib):
     prob = W.problem(64, 32, 8, U=0.3, n_sound=4)
     rc, h = _create(lib, 64, 32, 1.0, 0.3, prob["dt_f"], prob["dt_g"], 8,
                     n_sound=4)
+    assert rc == binding.PR_EUNSTABLE and not h.value
+    # the less diffusive G with a constant velocity
+    prob = W.problem(64, 32, 8, U=0.1)
+    rc, h = _create(lib, 64, 32, 1.0, 0.1, prob["dt_f"], prob["dt_g"], 8,
+                    n_sound=8, coarse_order=3)
     assert rc == binding.PR_EUNSTABLE and not h.value
 
 
