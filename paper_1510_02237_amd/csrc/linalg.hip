@@ -360,19 +360,44 @@ __global__ __launch_bounds__(256) void k_gemm_tn_mfma(
   const double* pb0 = B + (int64_t)rb0 * ldb + 4 * kq;
   const double* pb1 = B + (int64_t)rb1 * ldb + 4 * kq;
   d4 c00 = {0, 0, 0, 0}, c01 = c00, c10 = c00, c11 = c00;
+  // The second 16-row (16-column) block of the quarter is computed only if
+  // it reaches into M (N): an FP64 MFMA occupies the SIMD for 64 cycles,
+  // and small blocks (M, N <= 16) would otherwise spend three quarters of
+  // them on padding.  The blocks kept run the same MFMA sequence.
+  const bool m1 = m0 + 16 < M, n1 = n0 + 16 < N;
   // lda, ldb are multiples of 16 and the buffers are zero beyond d, so the
   // loop runs over whole groups of 16 without a tail.
   for (int64_t x = xs; x < xe; x += 16) {
     const d4 a0 = *(const d4*)(pa0 + x);
-    const d4 a1 = *(const d4*)(pa1 + x);
     const d4 b0 = *(const d4*)(pb0 + x);
-    const d4 b1 = *(const d4*)(pb1 + x);
+    if (m1 && n1) {
+      const d4 a1 = *(const d4*)(pa1 + x);
+      const d4 b1 = *(const d4*)(pb1 + x);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
-      c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], c01, 0, 0, 0);
-      c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], c10, 0, 0, 0);
-      c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], c11, 0, 0, 0);
+      for (int s = 0; s < 4; ++s) {
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], c01, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], c10, 0, 0, 0);
+        c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], c11, 0, 0, 0);
+      }
+    } else if (m1) {
+      const d4 a1 = *(const d4*)(pa1 + x);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], c10, 0, 0, 0);
+      }
+    } else if (n1) {
+      const d4 b1 = *(const d4*)(pb1 + x);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], c01, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
     }
   }
   double* W = work + (int64_t)split * M * N;
@@ -870,13 +895,21 @@ hipError_t launch_check_finite(const double* v, int64_t n, int* flag,
 }
 
 namespace {
+// Most splits of d: at least 1024 elements a split, but down to 256 while
+// that leaves at most 64 splits, so that small problems still spread over
+// several compute units.
+int64_t tn_max_splits(int64_t d) {
+  const int64_t big = (d + 1023) / 1024, small = (d + 255) / 256;
+  return std::max<int64_t>(big, std::min<int64_t>(small, 64));
+}
+
 void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
               int64_t* kc) {
   *mt = (M + TN_T - 1) / TN_T;
   *nt = (N + TN_T - 1) / TN_T;
   const int tiles = *mt * *nt;
   int64_t ns = (1024 + tiles - 1) / tiles;
-  const int64_t maxs = (d + 1023) / 1024;  // at least 1024 elements a split
+  const int64_t maxs = tn_max_splits(d);
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;
   int64_t k = (d + ns - 1) / ns;
@@ -888,11 +921,12 @@ void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
 
 // Upper bound of nsplit * M * N over every M <= Mmax, N <= Nmax at this d:
 // nsplit <= ceil(1024 / tiles) with M N <= 4096 tiles gives
-// (1024 + tiles) * 4096, and nsplit <= ceil(d / 1024) gives the second bound.
+// (1024 + tiles) * 4096, and nsplit <= tn_max_splits(d) gives the second
+// bound.
 size_t gemm_tn_work(int Mmax, int Nmax, int64_t d) {
   const int64_t tiles = (int64_t)((Mmax + TN_T - 1) / TN_T) * ((Nmax + TN_T - 1) / TN_T);
   const int64_t a = (1024 + tiles) * TN_T * TN_T;
-  const int64_t b = ((d + 1023) / 1024) * (int64_t)Mmax * Nmax;
+  const int64_t b = tn_max_splits(d) * (int64_t)Mmax * Nmax;
   return (size_t)std::min(a, b);
 }
 
