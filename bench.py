@@ -30,6 +30,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_POINT_STEP = 48.0   # read and write u, w, p once per RK-3 step
+# Stage form: stage 1 reads q^n and writes q*, stages 2 and 3 also read q^n
+# as their base: 48 + 72 + 72 bytes per point-step over three launches.
+STAGE_BYTES_PER_POINT_STEP = 192.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fine_step_traffic_c2_512x256.md")
 FINE_SRC = os.path.join(ROOT, "paper_1510_02237_amd", "csrc", "fine.hip")
 
@@ -80,9 +83,12 @@ def timed_solves(ctx, u0, K, out, n):
     return (time.perf_counter() - t0) * 1e3 / n, ms_fine, pts, st
 
 
-def serve_leg(n_req, rate, seed=4, timeout=300.0):
+def serve_leg(n_req, rate, seed=4, timeout=300.0, closed_loop=False):
     """Poisson stream of KSE-Parareal requests (grids 128x64..1024x512,
-    U in [0, 0.3], P in {8,...,64}, K = 4) through the server."""
+    U in [0, 0.3], P in {8,...,64}, K = 4) through the server.  With
+    closed_loop every request is submitted at once (the same seeded mix:
+    the draws do not depend on the rate) and solves/s is the server's
+    throughput."""
     import ctypes
     import numpy as np
     from paper_1510_02237_amd import binding, workloads as W
@@ -98,7 +104,8 @@ def serve_leg(n_req, rate, seed=4, timeout=300.0):
     t_start = time.perf_counter()
     try:
         for r, u0 in zip(reqs, states):
-            while time.perf_counter() - t_start < r["t_arrival"]:
+            while (not closed_loop
+                   and time.perf_counter() - t_start < r["t_arrival"]):
                 time.sleep(0.0005)
             p = r["prob"]
             o = binding.default_opts(nu_f=p["nu_f"], nu_c=p["nu_c"],
@@ -129,7 +136,9 @@ def serve_leg(n_req, rate, seed=4, timeout=300.0):
     finally:
         lib.pr_server_destroy(h)
     lat = np.array(lat) * 1e3
-    return dict(requests=n_req, arrival_rate_per_s=rate,
+    return dict(requests=n_req,
+                arrival_rate_per_s=None if closed_loop else rate,
+                closed_loop=closed_loop,
                 p50_ms=float(np.percentile(lat, 50)),
                 p99_ms=float(np.percentile(lat, 99)),
                 solves_per_s=n_req / wall, wall_s=wall)
@@ -190,9 +199,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2_512x256")
-    ap.add_argument("--serve", type=int, default=24,
+    ap.add_argument("--serve", type=int, default=48,
                     help="requests in the served-latency leg (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=6.0)
+    ap.add_argument("--serve-rate", type=float, default=None,
+                    help="arrival rate of the served stream (default: the "
+                         "frozen rate of workloads.SERVE_RATE)")
+    ap.add_argument("--serve-calibrate", action="store_true",
+                    help="run only the served stream closed-loop (every "
+                         "request at once) and print its throughput")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed batched solves (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -213,6 +227,13 @@ def main():
     import torch
     from paper_1510_02237_amd import binding, workloads as W
 
+    if args.serve_rate is None:
+        args.serve_rate = W.SERVE_RATE
+    if args.serve_calibrate:
+        out = serve_leg(args.serve, args.serve_rate, timeout=1e9,
+                        closed_loop=True)
+        print(json.dumps(out))
+        return
     if args.serve_only:
         out = serve_leg(args.serve, args.serve_rate, timeout=1e9)
         out["config"] = dict(workload="served stream", grids=list(W.SERVE_GRIDS),
@@ -229,10 +250,15 @@ def main():
     for _ in range(args.warmup):
         ctx.solve(u0_d, K, out=out)
     ms, ms_fine, pts, st = timed_solves(ctx, u0_d, K, out, args.steps)
-    n_fine_launches = args.steps * K * ctx_nf(prob)
+    stage = stage_form(prob)
+    # one fused launch (or three stage launches) per RK-3 step of every
+    # iteration of every window
+    n_fine_launches = (args.steps * prob.get("windows", 1) * min(K, prob["P"])
+                       * ctx_nf(prob) * (3 if stage else 1))
     kernel_ms = ms_fine / n_fine_launches
-    achieved = BYTES_PER_POINT_STEP * pts / (ms_fine * 1e-3) / 1e9
-    tb = measured_traffic()
+    bpp = STAGE_BYTES_PER_POINT_STEP if stage else BYTES_PER_POINT_STEP
+    achieved = bpp * pts / (ms_fine * 1e-3) / 1e9
+    tb = None if stage else measured_traffic()
     traffic = None if tb is None else tb * pts / n_fine_launches
     res = dict(
         metric="Parareal wall-time vs serial fine on GPU; stencil GB/s; "
@@ -243,17 +269,20 @@ def main():
         config=dict(workload=args.workload, grid=[prob["nx"], prob["nz"]],
                     P=prob["P"], K=K, U=prob["U"], c_s=prob["c_s"],
                     T=prob["T"], n_f=ctx_nf(prob), n_g=ctx_ng(prob),
-                    form="batched", parallelism="time slices x tiles, 1 GPU"),
+                    windows=prob.get("windows", 1),
+                    form="stagewise" if stage else "batched",
+                    parallelism="time slices x tiles, 1 GPU"),
         phases_ms=dict(coarse_init=st["ms_coarse_init"], fine=st["ms_fine"],
                        update=st["ms_update"], chain=st["ms_chain"],
                        total=st["ms_total"]),
         ranks=st["rank"],
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS,
                       unit="GB/s", frac=achieved / HBM_PEAK_GBPS,
-                      traffic=traffic, kernel="k_fine_step",
+                      traffic=traffic,
+                      kernel="k_stage" if stage else "k_fine_step",
                       kernel_avg_ms=kernel_ms,
-                      bytes_per_point_step=BYTES_PER_POINT_STEP,
-                      algorithmic_bytes_per_launch=BYTES_PER_POINT_STEP * pts / n_fine_launches,
+                      bytes_per_point_step=bpp,
+                      algorithmic_bytes_per_launch=bpp * pts / n_fine_launches,
                       fine_hip_sha256_16=fine_src_hash()),
         fine_point_updates_per_s=pts / (ms_fine * 1e-3),
     )
@@ -295,6 +324,15 @@ def main():
         torch.cuda.synchronize()
         res["calibration_copy_bytes"] = n * 8
     print(json.dumps(res))
+
+
+def stage_form(prob):
+    """True when the fine sweep of this workload runs as three stage
+    launches per RK-3 step (per-row and per-column advective weights: the
+    Section 3.1 pair, a z-velocity, a rotation or second-order acoustics)."""
+    return (prob.get("scheme", "split") == "rk3" or prob.get("V", 0.0) != 0.0
+            or prob.get("gamma", 0.0) != 0.0
+            or prob.get("fine_acoustic_order", 4) == 2)
 
 
 def ctx_nf(prob):

@@ -212,6 +212,11 @@ def config(name):
 
 
 SERVE_GRIDS = ((128, 64), (256, 128), (512, 256), (1024, 512))
+# Arrival rate of the served stream (requests per second): 0.8 times the
+# closed-loop throughput of the same seeded mix, 8.0 solves/s on one MI355X
+# with 64 requests submitted at once (bench.py --serve-calibrate --serve 64),
+# measured once and frozen here.
+SERVE_RATE = 6.4
 SERVE_SLICES = (8, 16, 32, 64)
 
 
