@@ -43,3 +43,25 @@ def test_fixed_K_reports_no_residual():
     # a tolerance that is never reached gives the fixed-K result bitwise
     b = binding.Context.from_problem(prob, stop_tol=1e-300).solve(u0, K)
     assert np.array_equal(a, b)
+
+
+def test_stopping_with_rotation_and_windows():
+    """Three windows of the paper's rotating-flow run (Section 3.2) with
+    the stopping criterion: each window stops where the oracle's does.  The
+    tolerance 3e-2 lies at least 40 % away from every residual of the three
+    windows (0.25 ... 4.3e-3), so the decision does not hinge on rounding;
+    every window stops after its fourth iteration."""
+    prob, K, u0 = W.config("rot_40x40")
+    prob = dict(prob, windows=3)
+    prob["T"] = 3 * prob["P"] * prob["dt_g"]
+    prm = Params(**prob)
+    tol = 3e-2
+    want = oracle.kse_parareal(u0, prm, K=5, stop_tol=tol)
+    say("stopping with rotation and windows")
+    ctx = binding.Context.from_problem(prob, stop_tol=tol)
+    got = ctx.solve(u0, 5)
+    st = ctx.stats()
+    assert st["iterations"] == want["iterations"] == 4
+    assert rel_l2(got, want["q"][prm.P]) <= 1e-10
+    for a, b in zip(st["residual"], want["residuals"]):
+        assert abs(a - b) <= 1e-9 * b
