@@ -230,15 +230,19 @@ int pr_set_mfma(pr_ctx* ctx, int32_t on);
 
 /* Fine propagator over one slice for `nslices` independent states
  * (Algorithm 2, parallel predictor step; F of Section 3.2: n_f steps of the
- * three-stage Runge-Kutta scheme with 5th-order upwind advection, 4th-order
- * centred acoustic terms and divergence damping nu_f).
+ * three-stage Runge-Kutta scheme with 5th-order upwind advection along the
+ * velocity of pr_opts (U, V, gamma), centred acoustic terms of order
+ * opts.fine_acoustic_order and divergence damping nu_f; with
+ * PR_SCHEME_RK3 the F of Section 3.1).
  * Q, FQ: [nslices][3][nz][nx]; FQ[s] = F(Q[s]).  Q and FQ must not overlap.
  * The launch form follows opts.form.  1 <= nslices <= 4096. */
 int pr_fine_sweep(pr_ctx* ctx, const double* Q, double* FQ, int32_t nslices,
                   int mem);
 
 /* Coarse propagator over one slice (n_g partially split forward-Euler steps
- * with N_sound forward-backward acoustic substeps, Section 3.2), or, with
+ * with N_sound forward-backward acoustic substeps and the upwind slow
+ * tendency of order opts.coarse_order, Section 3.2; with PR_SCHEME_RK3 the
+ * G of Section 3.1), or, with
  * use_krylov != 0, the modified coarse propagator of eq. modifiedCoarse,
  * K(q) = G((I - P)q) + F(P q), with the context's current basis (eq.
  * Genhance).  q, gq: one state each; they may alias. */
