@@ -694,8 +694,11 @@ __global__ __launch_bounds__(64) void k_pchol_wave(
   int rho = b;
   for (int k = 0; k < b; ++k) {
     if (pivot) {
+      // The search starts at position k, a valid index: when no diagonal
+      // exceeds -1 (a non-finite Gram) the reduction returns k, its
+      // threshold test fails and the factorisation ends with rank k.
       double best = -1.0;
-      int bi = b;
+      int bi = k;
       for (int q = k + t; q < b; q += 64)
         if (diag[q] > best) { best = diag[q]; bi = q; }
 #pragma unroll
