@@ -95,7 +95,8 @@ def test_c1_solve_matches_oracle(form):
 
 @pytest.mark.parametrize("nx,nz,P,U,K", [(16, 8, 4, -0.2, 2), (8, 8, 1, 0.1, 1),
                                          (40, 24, 6, 0.25, 3),
-                                         (130, 20, 5, 0.05, 2)])
+                                         (130, 20, 5, 0.05, 2),
+                                         (24, 16, 8, 0.0, 3)])
 def test_solve_matches_oracle(nx, nz, P, U, K):
     prob = small_problem(nx, nz, P, U=U)
     u0 = smooth_state(prob, 7)
@@ -103,6 +104,21 @@ def test_solve_matches_oracle(nx, nz, P, U, K):
     want = _oracle_solve(prob, u0, K)
     ctx = binding.Context.from_problem(prob)
     assert rel_l2(ctx.solve(u0, K), want["q"][-1]) <= TOL_FINAL
+    assert ctx.stats()["rank"] == want["ranks"]
+
+
+def test_many_slices_matches_oracle():
+    """P = 64 slices of two coarse steps at U = 0.3 (N_sound = 10: three
+    substep launches per coarse step with the stored slow tendency): the
+    kept directions stay above 7.8e-6 of |R_11| and the dropped ones below
+    1e-16 in the oracle's QR, so both rank rules give 64, 127."""
+    prob = small_problem(64, 32, 64, U=0.3, n_g=2)
+    u0 = smooth_state(prob, 7)
+    say("solve 64x32 P=64 K=2")
+    want = _oracle_solve(prob, u0, 2)
+    assert want["ranks"] == [64, 127]
+    ctx = binding.Context.from_problem(prob)
+    assert rel_l2(ctx.solve(u0, 2), want["q"][-1]) <= TOL_FINAL
     assert ctx.stats()["rank"] == want["ranks"]
 
 
