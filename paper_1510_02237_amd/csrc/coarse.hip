@@ -48,7 +48,16 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   const int nx = L.nx, nz = L.nz;
   const int64_t n = (int64_t)nx * nz;
   const int xtiles = (nx + TX - 1) / TX;
-  const int xt = blockIdx.x % xtiles, zt = blockIdx.x / xtiles;
+  // Workgroups go to the 8 XCDs round-robin; give each XCD a contiguous
+  // range of tiles, so that the halo a tile reads was mostly written by
+  // the same XCD in the previous step and sits in its L2.  The grid is
+  // padded to a multiple of 8; blocks past the last tile leave before any
+  // barrier.
+  const int ntiles = xtiles * ((nz + TZ - 1) / TZ);
+  const int per = (ntiles + 7) >> 3;
+  const int lt = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lt >= ntiles) return;
+  const int xt = lt % xtiles, zt = lt / xtiles;
   const int64_t off = (int64_t)blockIdx.y * L.stride;
   const double* __restrict__ in = L.in + off;
   double* __restrict__ out = L.out + off;
@@ -193,12 +202,13 @@ hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s) {
   if (L.nsub < 1 || L.nsub > kCoarseMaxSubPerLaunch || L.nstates < 1)
     return hipErrorInvalidValue;
   const int big = ((L.nx + 31) / 32) * ((L.nz + 31) / 32);
+  auto pad8 = [](int t) { return (unsigned)(8 * ((t + 7) / 8)); };
   if ((int64_t)big * L.nstates < 256) {
     const int tiles = ((L.nx + 31) / 32) * ((L.nz + 15) / 16);
-    hipLaunchKernelGGL((k_coarse<32, 16, 1024>), dim3(tiles, L.nstates),
+    hipLaunchKernelGGL((k_coarse<32, 16, 1024>), dim3(pad8(tiles), L.nstates),
                        dim3(1024), 0, s, L);
   } else {
-    hipLaunchKernelGGL((k_coarse<32, 32, 1024>), dim3(big, L.nstates),
+    hipLaunchKernelGGL((k_coarse<32, 32, 1024>), dim3(pad8(big), L.nstates),
                        dim3(1024), 0, s, L);
   }
   return hipGetLastError();
