@@ -19,6 +19,10 @@
 // x-halo at all: the three columns beyond each end of an LDS row hold copies
 // of the columns at the other end, written with the row, so every thread
 // computes an output column.
+//
+// Odd chunks march upwards, so that the halo rows two neighbouring chunks
+// share are read by both at the same time (both at the start or both at the
+// end of their march) and the second read hits in L2.
 #include "pr_internal.h"
 
 namespace prh {
@@ -93,55 +97,67 @@ struct Carry {
 };
 
 // LDS ring layout: column-major, one LDS column of CS doubles per x
-// position holding the 3 levels x 4 row slots x 3 fields of that position
-// (CS odd, so 16 consecutive lanes reading 8-byte words hit distinct bank
-// pairs).  A thread addresses everything from one base, its own column, with
-// small constant offsets: value (level, slot, field) of column c + dx is at
-// base + dx * CS + (level * 4 + slot) * 3 + field.
-constexpr int CS = 37;
+// position holding the 3 levels x 4 row slots of that position.  The pair
+// (u, w) of ring row s = level * 4 + slot sits at 2 s, 16-byte aligned, so
+// one 128-bit read fetches both; p sits at 24 + s.  With CS = 38 a column
+// starts every 304 bytes: 16 consecutive lanes of a 128-bit read start on
+// distinct groups of 4 banks, and of a 64-bit read on distinct bank pairs.
+// A thread addresses everything from one base, its own column, with small
+// constant offsets.
+constexpr int CS = 38;
+constexpr int PB = 24;  // p of ring row s at PB + s
 
-// Reads u, w at offsets +-1 of the next row (rn: own column of that row).
+__device__ __forceinline__ double2 ld2(const double* a) {
+  return *reinterpret_cast<const double2*>(a);
+}
+
+// Reads u, w at offsets +-1 of the next row (rn: (u, w) pair of the own
+// column of that row).
 __device__ __forceinline__ void carry_read(const double* rn, double& um,
                                            double& up, double& wm,
                                            double& wp) {
-  um = rn[-CS];
-  up = rn[CS];
-  wm = rn[1 - CS];
-  wp = rn[1 + CS];
+  const double2 m = ld2(rn - CS), q = ld2(rn + CS);
+  um = m.x;
+  wm = m.y;
+  up = q.x;
+  wp = q.y;
 }
 
-// Right-hand side at one point of row r.  rc: this thread's column of LDS
-// row r of the level (fields u, w, p at rc[0], rc[1], rc[2]);
+// Right-hand side at one point of row r.  rc: this thread's (u, w) pair of
+// LDS row s = r's ring row of the level, p at rc[PB - s];
 // the own-column values along z come from registers, the +-1 neighbours
 // of u and w and the D differences from the carry, D_u, D_w of row r + 1
 // from the caller.
 template <int SGN>
 __device__ __forceinline__ void rhs_point(
-    const double* rc, const Carry& cy, double dup, double dwp,
+    const double* rc, const double* rp, const Carry& cy, double dup,
+    double dwp,
     double u0, double wm2, double wm1, double w0, double wp1, double wp2,
     double pm2, double pm1, double p0, double pp1, double pp2,
     const FusedCoef& k, double& fu, double& fw, double& fp) {
-  // field f at x-offset dx
-  auto U = [&](int dx) { return rc[dx * CS]; };
-  auto Wr = [&](int dx) { return rc[dx * CS + 1]; };
-  auto Pr = [&](int dx) { return rc[dx * CS + 2]; };
+  // (u, w) pair and p at x-offset dx
+  auto UW = [&](int dx) { return ld2(rc + dx * CS); };
+  auto Pr = [&](int dx) { return rp[dx * CS]; };
   const double um1 = cy.xum, up1 = cy.xup, wxm1 = cy.xwm, wxp1 = cy.xwp;
-  const double um2 = U(-2), up2 = U(2);
-  const double wxm2 = Wr(-2), wxp2 = Wr(2);
+  const double2 m2 = UW(-2), p2 = UW(2);
+  const double um2 = m2.x, up2 = p2.x;
+  const double wxm2 = m2.y, wxp2 = p2.y;
   const double pxm2 = Pr(-2), pxm1 = Pr(-1), pxp1 = Pr(1), pxp2 = Pr(2);
   double au, aw, ap;
   if (SGN > 0) {  // offsets -3 .. +2
-    au = k.a0 * U(-3) + k.a1 * um2 + k.um * um1 + k.uc * u0 + k.up * up1 +
+    const double2 m3 = UW(-3);
+    au = k.a0 * m3.x + k.a1 * um2 + k.um * um1 + k.uc * u0 + k.up * up1 +
          k.a5 * up2;
-    aw = k.a0 * Wr(-3) + k.a1 * wxm2 + k.a2 * wxm1 + k.wc * w0 +
+    aw = k.a0 * m3.y + k.a1 * wxm2 + k.a2 * wxm1 + k.wc * w0 +
          k.a4 * wxp1 + k.a5 * wxp2;
     ap = k.a0 * Pr(-3) + k.a1 * pxm2 + k.a2 * pxm1 + k.a3 * p0 +
          k.a4 * pxp1 + k.a5 * pxp2;
   } else {  // offsets -2 .. +3
+    const double2 p3 = UW(3);
     au = k.a0 * um2 + k.um * um1 + k.uc * u0 + k.up * up1 + k.a4 * up2 +
-         k.a5 * U(3);
+         k.a5 * p3.x;
     aw = k.a0 * wxm2 + k.a1 * wxm1 + k.wc * w0 + k.a3 * wxp1 + k.a4 * wxp2 +
-         k.a5 * Wr(3);
+         k.a5 * p3.y;
     ap = k.a0 * pxm2 + k.a1 * pxm1 + k.a2 * p0 + k.a3 * pxp1 + k.a4 * pxp2 +
          k.a5 * Pr(3);
   }
@@ -163,7 +179,7 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
   constexpr int PAD = 3;
   constexpr int W = NT + 2 * PAD;
   static_assert(4 % PF == 0, "prefetch depth must divide the 4-row tail");
-  __shared__ double ring[W * CS];  // column-major, see CS
+  __shared__ __align__(16) double ring[W * CS];  // column-major, see CS
 
   const int lb = xcd_logical_block(L.nblocks);
   if (lb >= L.nblocks) return;
@@ -181,7 +197,13 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
   const int64_t n = (int64_t)nx * nz;
   const double* __restrict__ in = J.in + sl * J.in_stride;
   double* __restrict__ out = J.out + sl * J.out_stride;
-  const FusedCoef k = load_fused_coef<SGN>(J.c);
+  // Odd chunks march upwards (decreasing z), so that two neighbouring
+  // chunks read the rows they share at the same time.  Marching backwards
+  // flips the sign of every odd z-difference; negating their coefficients
+  // gives bitwise the same results.
+  const bool rev = (zt & 1) != 0;
+  FusedCoef k = load_fused_coef<SGN>(J.c);
+  if (rev) { k.cz4 = -k.cz4; k.kxzu = -k.kxzu; k.kxzw = -k.kxzw; }
   const double dt = J.c.dt;
   const double b1 = dt / 3.0, b2 = 0.5 * dt;
 
@@ -190,6 +212,8 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
   const int zc = L.zc;
   const int x0 = xt * TX;
   const int z0 = zt * zc;
+  const int zdir = rev ? -1 : 1;
+  const int zbase = rev ? z0 + zc + 5 : z0 - 6;  // input row of iteration 0
   const int gx = FULL ? t : wrap(x0 - 3 * HL + t, nx);
   const int xo = FULL ? t : x0 + t - 3 * HL;
   const bool store_col =
@@ -205,12 +229,14 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
     ring[(col < PAD ? col : NT + col) * CS + e] = 0.0;
   }
   double* const own = ring + c * CS;  // this thread's LDS column
-  auto slot = [&](int lvl, int sl) { return own + (lvl * 4 + sl) * 3; };
+  // (u, w) pair and p of ring row (level, slot)
+  auto slot = [&](int lvl, int sl) { return own + 2 * (lvl * 4 + sl); };
+  auto pslot = [&](int lvl, int sl) { return own + PB + lvl * 4 + sl; };
 
   double fu_[PF], fw_[PF], fp_[PF];  // prefetched input rows
 #pragma unroll
   for (int q = 0; q < PF; ++q) {
-    const double* src = in + (int64_t)wrap(z0 - 6 + q, nz) * nx + gx;
+    const double* src = in + (int64_t)wrap(zbase + zdir * q, nz) * nx + gx;
     fu_[q] = src[0];
     fw_[q] = src[n];
     fp_[q] = src[2 * n];
@@ -223,15 +249,14 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
 
   // Writes this thread's column of one ring row (and, for FULL, its copy in
   // the pad at the other end of the row).
-  auto ring_put = [&](double* r, double vu, double vw, double vp) {
-    r[0] = vu;
-    r[1] = vw;
-    r[2] = vp;
+  auto ring_put = [&](double* r, double* rp, double vu, double vw,
+                      double vp) {
+    *reinterpret_cast<double2*>(r) = double2{vu, vw};
+    *rp = vp;
     if (FULL && (pad_lo || pad_hi)) {
-      double* rr = r + (pad_lo ? NT : -NT) * CS;
-      rr[0] = vu;
-      rr[1] = vw;
-      rr[2] = vp;
+      const int o = (pad_lo ? NT : -NT) * CS;
+      *reinterpret_cast<double2*>(r + o) = double2{vu, vw};
+      rp[o] = vp;
     }
   };
 
@@ -251,7 +276,8 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
     const double dup = xup - xum, dwp = xwp - xwm;                            \
     if (DO) {                                                                 \
       double fu, fw, fp;                                                      \
-      rhs_point<SGN>(slot(LVL, ((uu) - 2) & 3), CY, dup, dwp,                 \
+      rhs_point<SGN>(slot(LVL, ((uu) - 2) & 3), pslot(LVL, ((uu) - 2) & 3),   \
+                     CY, dup, dwp,                                            \
                         ZU[((uu) - 2) & 7], ZW[((uu) - 4) & 7],               \
                         ZW[((uu) - 3) & 7], ZW[((uu) - 2) & 7],               \
                         ZW[((uu) - 1) & 7], ZW[(uu) & 7], ZP[((uu) - 4) & 7], \
@@ -279,9 +305,9 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
       iu[uu] = fu_[q];                                                        \
       iw[uu] = fw_[q];                                                        \
       ip[uu] = fp_[q];                                                        \
-      ring_put(slot(0, (uu) & 3), iu[uu], iw[uu], ip[uu]);                    \
+      ring_put(slot(0, (uu) & 3), pslot(0, (uu) & 3), iu[uu], iw[uu], ip[uu]); \
       const int zp = (it) + PF < nrows ? (it) + PF : nrows - 1;               \
-      const double* src = in + (int64_t)wrap(z0 - 6 + zp, nz) * nx + gx;      \
+      const double* src = in + (int64_t)wrap(zbase + zdir * zp, nz) * nx + gx; \
       fu_[q] = src[0];                                                        \
       fw_[q] = src[n];                                                        \
       fp_[q] = src[2 * n];                                                    \
@@ -289,14 +315,14 @@ __global__ __launch_bounds__(NT, NT >= 512 ? 1 : 2) void k_fine_step(
     PR_STAGE(P1, D1, 0, c1, iu, iw, ip, iu[((uu) - 2) & 7],                   \
              iw[((uu) - 2) & 7], ip[((uu) - 2) & 7], au, aw, ap, b1,          \
              au[uu] = nu; aw[uu] = nw; ap[uu] = np;                           \
-             ring_put(slot(1, (uu) & 3), nu, nw, np);)                        \
+             ring_put(slot(1, (uu) & 3), pslot(1, (uu) & 3), nu, nw, np);)    \
     PR_STAGE(P2, D2, 1, c2, au, aw, ap, iu[((uu) - 4) & 7],                   \
              iw[((uu) - 4) & 7], ip[((uu) - 4) & 7], bu, bw, bp, b2,          \
              bu[uu] = nu; bw[uu] = nw; bp[uu] = np;                           \
-             ring_put(slot(2, (uu) & 3), nu, nw, np);)                        \
+             ring_put(slot(2, (uu) & 3), pslot(2, (uu) & 3), nu, nw, np);)    \
     PR_STAGE(P3, D3, 2, c3, bu, bw, bp, iu[((uu) - 6) & 7],                   \
              iw[((uu) - 6) & 7], ip[((uu) - 6) & 7], bu, bw, bp, dt,          \
-             const int z3 = z0 + (it) - 12;                                   \
+             const int z3 = zbase + zdir * ((it) - 6);                        \
              if (store_col && (it) < nrows && z3 < nz) {                      \
                double* dst = out + (int64_t)z3 * nx + xo;                     \
                dst[0] = nu;                                                   \
