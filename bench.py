@@ -34,6 +34,7 @@ BYTES_PER_POINT_STEP = 48.0   # read and write u, w, p once per RK-3 step
 # as their base: 48 + 72 + 72 bytes per point-step over three launches.
 STAGE_BYTES_PER_POINT_STEP = 192.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fine_step_traffic_c2_512x256.md")
+TRAFFIC_WORKLOAD = "c2_512x256"  # the workload the counters were taken on
 FINE_SRC = os.path.join(ROOT, "paper_1510_02237_amd", "csrc", "fine.hip")
 
 
@@ -258,7 +259,10 @@ def main():
     kernel_ms = ms_fine / n_fine_launches
     bpp = STAGE_BYTES_PER_POINT_STEP if stage else BYTES_PER_POINT_STEP
     achieved = bpp * pts / (ms_fine * 1e-3) / 1e9
-    tb = None if stage else measured_traffic()
+    # the counters hold for the tile and chunk shape of the workload they
+    # were taken on; other grids use other tiles
+    tb = (measured_traffic()
+          if not stage and args.workload == TRAFFIC_WORKLOAD else None)
     traffic = None if tb is None else tb * pts / n_fine_launches
     res = dict(
         metric="Parareal wall-time vs serial fine on GPU; stencil GB/s; "
