@@ -2,7 +2,10 @@
 oracle: relative l2 error <= 1e-12 per fine sweep and per coarse step, on
 grids that span several workgroup tiles with ragged edges in x and z, both
 signs of U, every launch form and every tile shape (bitwise equal among the
-fused forms and shapes)."""
+fused forms and shapes).  The fused step marches odd chunks upwards; the
+chunk heights below give several chunks per slice with a ragged last chunk
+that is odd for some of them, so both directions and the ragged upward
+chunk are compared with the oracle and with each other."""
 
 import numpy as np
 import pytest
