@@ -366,38 +366,51 @@ __global__ __launch_bounds__(256) void k_gemm_tn_mfma(
   // them on padding.  The blocks kept run the same MFMA sequence.
   const bool m1 = m0 + 16 < M, n1 = n0 + 16 < N;
   // lda, ldb are multiples of 16 and the buffers are zero beyond d, so the
-  // loop runs over whole groups of 16 without a tail.
+  // loop runs over whole groups of 16 without a tail.  The operands of the
+  // next group are loaded before the MFMAs of the current one, so each wave
+  // keeps two groups of loads in flight.  The blocks not computed load
+  // nothing (their operands stay zero and unused).
+  const d4 z4 = {0, 0, 0, 0};
+  d4 a0 = z4, b0 = z4, a1 = z4, b1 = z4;
+  if (xs < xe) {
+    a0 = *(const d4*)(pa0 + xs);
+    b0 = *(const d4*)(pb0 + xs);
+    if (m1) a1 = *(const d4*)(pa1 + xs);
+    if (n1) b1 = *(const d4*)(pb1 + xs);
+  }
   for (int64_t x = xs; x < xe; x += 16) {
-    const d4 a0 = *(const d4*)(pa0 + x);
-    const d4 b0 = *(const d4*)(pb0 + x);
+    const d4 ca0 = a0, cb0 = b0, ca1 = a1, cb1 = b1;
+    const int64_t xn = x + 16;
+    if (xn < xe) {
+      a0 = *(const d4*)(pa0 + xn);
+      b0 = *(const d4*)(pb0 + xn);
+      if (m1) a1 = *(const d4*)(pa1 + xn);
+      if (n1) b1 = *(const d4*)(pb1 + xn);
+    }
     if (m1 && n1) {
-      const d4 a1 = *(const d4*)(pa1 + x);
-      const d4 b1 = *(const d4*)(pb1 + x);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], c01, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], c10, 0, 0, 0);
-        c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b1[s], c11, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[s], cb0[s], c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[s], cb1[s], c01, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[s], cb0[s], c10, 0, 0, 0);
+        c11 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[s], cb1[s], c11, 0, 0, 0);
       }
     } else if (m1) {
-      const d4 a1 = *(const d4*)(pa1 + x);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
-        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[s], b0[s], c10, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[s], cb0[s], c00, 0, 0, 0);
+        c10 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca1[s], cb0[s], c10, 0, 0, 0);
       }
     } else if (n1) {
-      const d4 b1 = *(const d4*)(pb1 + x);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
-        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b1[s], c01, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[s], cb0[s], c00, 0, 0, 0);
+        c01 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[s], cb1[s], c01, 0, 0, 0);
       }
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[s], b0[s], c00, 0, 0, 0);
+        c00 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca0[s], cb0[s], c00, 0, 0, 0);
     }
   }
   double* W = work + (int64_t)split * M * N;
@@ -485,14 +498,23 @@ __global__ __launch_bounds__(256) void k_gemm_nn_mfma(
     }
     __syncthreads();
     if (active) {
+      // All loads of the chunk are issued before its MFMAs, so that a wave
+      // keeps NN_JC / 4 of them in flight; rows past K contribute zero
+      // (their rows of C in LDS are zero too).
+      double bv[NN_JC / 4];
+#pragma unroll
+      for (int u = 0; u < NN_JC / 4; ++u) {
+        const int j = j0 + 4 * u + kq;
+        bv[u] = j < K ? pa[(int64_t)j * lda] : 0.0;
+      }
       const int jn = K - j0 < NN_JC ? K - j0 : NN_JC;
-      for (int jj = 0; jj < jn; jj += 4) {
-        const int j = j0 + jj + kq;
-        const double bv = j < K ? pa[(int64_t)j * lda] : 0.0;
+#pragma unroll
+      for (int u = 0; u < NN_JC / 4; ++u) {
+        if (4 * u >= jn) break;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          const double av = cs[jj + kq][b * 16 + r16];
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+          const double av = cs[4 * u + kq][b * 16 + r16];
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[u], acc[b], 0, 0, 0);
         }
       }
     }
