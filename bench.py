@@ -287,6 +287,7 @@ def main():
                       kernel_avg_ms=kernel_ms,
                       bytes_per_point_step=bpp,
                       algorithmic_bytes_per_launch=bpp * pts / n_fine_launches,
+                      tile=None if stage else [st["tile_nt"], st["tile_zc"]],
                       fine_hip_sha256_16=fine_src_hash()),
         fine_point_updates_per_s=pts / (ms_fine * 1e-3),
     )

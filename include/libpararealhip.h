@@ -178,6 +178,11 @@ typedef struct pr_stats {
   int64_t fine_point_steps; /* grid points x RK-3 steps done by the sweeps */
   double residual[64];      /* r^k after iteration k (k < 64) when
                                stop_tol > 0, else 0                        */
+  int32_t tile_nt, tile_zc; /* tile of the fused fine step in the sweep
+                               over the most slices (threads per workgroup,
+                               output rows per workgroup), as set in
+                               pr_opts or chosen by the autotuner; 0 when
+                               the sweeps ran in the stage form           */
 } pr_stats;
 
 /* Fills the defaults listed above. */

@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("iterations", ctypes.c_int32),
                 ("rank", ctypes.c_int32 * 64),
                 ("fine_point_steps", ctypes.c_int64),
-                ("residual", ctypes.c_double * 64)]
+                ("residual", ctypes.c_double * 64),
+                ("tile_nt", ctypes.c_int32), ("tile_zc", ctypes.c_int32)]
 
 
 _lib = None
@@ -323,4 +324,5 @@ class Context:
                     ms_chain=s.ms_chain, iterations=s.iterations,
                     rank=list(s.rank[:s.iterations]),
                     fine_point_steps=s.fine_point_steps,
-                    residual=list(s.residual[:s.iterations]))
+                    residual=list(s.residual[:s.iterations]),
+                    tile_nt=s.tile_nt, tile_zc=s.tile_zc)

@@ -989,6 +989,13 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
   }
   c->stats.ms_total = el(0, 2 + 3 * Keff);
   c->stats.fine_point_steps = pts;
+  if (form != PR_FORM_STAGEWISE && Keff > 0) {
+    // the first sweep covers the most slices (the plain form tunes for one)
+    int nt = 0, zc = 0;
+    tile_for(c, form == PR_FORM_PLAIN ? 1 : P, &nt, &zc);
+    c->stats.tile_nt = nt;
+    c->stats.tile_zc = zc;
+  }
   if (U_K) RC(copy_state_out(c, U_K, c->Q + (int64_t)P * ld, mem));
   if (slices) {
     HC(hipMemcpy2DAsync(slices, (size_t)c->d * 8, c->Q, (size_t)ld * 8,
@@ -1027,6 +1034,8 @@ static int solve_impl(pr_ctx* c, const double* u0, int32_t K, double* U_K,
     acc.fine_point_steps += c->stats.fine_point_steps;
   }
   acc.iterations = c->stats.iterations;
+  acc.tile_nt = c->stats.tile_nt;
+  acc.tile_zc = c->stats.tile_zc;
   std::memcpy(acc.rank, c->stats.rank, sizeof acc.rank);
   std::memcpy(acc.residual, c->stats.residual, sizeof acc.residual);
   c->stats = acc;

@@ -112,3 +112,23 @@ def test_serial_fine_matches_oracle():
     for ns in (1, 3, 4):
         want = oracle.serial_fine(u0, prm, nslices=ns)
         assert rel_l2(ctx.serial_fine(u0, ns), want) <= TOL_SWEEP
+
+
+def test_stats_report_the_fine_tile():
+    """pr_stats names the fused-step tile of the solve: the one set in the
+    options, else the autotuner's choice; none in the stage form."""
+    prob = small_problem(100, 40, 4, U=0.1)
+    u0 = smooth_state(prob, 1)
+    say("stats tile")
+    ctx = binding.Context.from_problem(prob, tile_nt=192, tile_zc=28)
+    ctx.solve(u0, 2)
+    st = ctx.stats()
+    assert (st["tile_nt"], st["tile_zc"]) == (192, 28)
+    ctx = binding.Context.from_problem(prob)
+    ctx.solve(u0, 2)
+    st = ctx.stats()
+    assert st["tile_nt"] in (128, 192, 256), st
+    assert st["tile_zc"] > 0 and st["tile_zc"] % 4 == 0, st
+    stw = binding.Context.from_problem(prob, form="stagewise")
+    stw.solve(u0, 2)
+    assert (stw.stats()["tile_nt"], stw.stats()["tile_zc"]) == (0, 0)
