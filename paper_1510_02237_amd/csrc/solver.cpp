@@ -920,9 +920,14 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
     if (form == PR_FORM_BATCHED)
       RC(with_graph(c, gkey(2, i0, 0), sweep));
     else if (form == PR_FORM_STAGEWISE) {
+      // the stage buffers are allocated before the capture; growing them
+      // later drops the captured graphs
       RC(ensure_ext(c, &c->ext_ping, &c->ext_ping_len, (size_t)3 * ns * ld));
-      RC(run_sweep(c, c->Q + (int64_t)i0 * ld, ld, c->Qt + (int64_t)(i0 + 1) * ld,
-                   ld, c->ext_ping, ld, ns, form));
+      RC(with_graph(c, gkey(5, i0, 0), [&] {
+        return run_sweep(c, c->Q + (int64_t)i0 * ld, ld,
+                         c->Qt + (int64_t)(i0 + 1) * ld, ld, c->ext_ping, ld,
+                         ns, form);
+      }));
     } else
       RC(sweep());
     pts += (int64_t)ns * c->n * c->n_f;
@@ -1307,11 +1312,10 @@ extern "C" int pr_serial_fine(pr_ctx* c, const double* u0, int32_t nslices,
       RC(run_sweep(c, a, c->ld, b, c->ld, ping, c->ld, 1, form));
       return run_sweep(c, b, c->ld, a, c->ld, ping, c->ld, 1, form);
     };
-    if (form == PR_FORM_BATCHED) {
-      for (int p = 0; p < pairs; ++p) RC(with_graph(c, gkey(4, 0, 0), two));
-    } else {
-      for (int p = 0; p < pairs; ++p) RC(two());
-    }
+    // one graph per form: the batched and the stage form capture
+    // different launches over the same buffers
+    const long long key = gkey(form == PR_FORM_BATCHED ? 4 : 6, 0, 0);
+    for (int p = 0; p < pairs; ++p) RC(with_graph(c, key, two));
   }
   double* res = a;
   if (nslices % 2) {
