@@ -923,9 +923,17 @@ namespace {
 // Most splits of d: at least 1024 elements a split, but down to 256 while
 // that leaves at most 64 splits, so that small problems still spread over
 // several compute units.
-int64_t tn_max_splits(int64_t d) {
+// Splits of d for a product with `tiles` 64 x 64 tiles: about 1024
+// workgroups, chunks of at least 1024 elements (or 256 for small d).
+int64_t tn_tile_splits(int64_t d, int tiles) {
   const int64_t big = (d + 1023) / 1024, small = (d + 255) / 256;
-  return std::max<int64_t>(big, std::min<int64_t>(small, 64));
+  const int64_t maxs = std::max<int64_t>(big, std::min<int64_t>(small, 64));
+  return std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, maxs));
+}
+
+// Upper bound of the splits tn_shape picks at this d.
+int64_t tn_max_splits(int64_t d) {
+  return std::max<int64_t>(tn_tile_splits(d, 1), (d + 511) / 512);
 }
 
 void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
@@ -933,10 +941,16 @@ void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
   *mt = (M + TN_T - 1) / TN_T;
   *nt = (N + TN_T - 1) / TN_T;
   const int tiles = *mt * *nt;
-  int64_t ns = (1024 + tiles - 1) / tiles;
-  const int64_t maxs = tn_max_splits(d);
-  if (ns > maxs) ns = maxs;
-  if (ns < 1) ns = 1;
+  int64_t ns = tn_tile_splits(d, tiles);
+  // A wave computes one 32 x 32 quarter of a tile, and quarters beyond M
+  // or N exit at once.  A small product (one or two active quarters per
+  // split) takes more, shorter chunks, down to 512 elements, so that about
+  // 1024 waves load operands at once; the partials to sum grow with them.
+  // active >= tiles, so ns stays <= ceil(1024 / tiles).
+  const int64_t active = (int64_t)((M + 31) / 32) * ((N + 31) / 32);
+  if (active <= 2)
+    ns = std::max<int64_t>(ns, std::min<int64_t>((1024 + active - 1) / active,
+                                                 (d + 511) / 512));
   int64_t k = (d + ns - 1) / ns;
   k = (k + 15) / 16 * 16;
   *kc = k;
