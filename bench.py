@@ -120,6 +120,10 @@ def serve_leg(n_req, rate, seed=4, timeout=300.0, closed_loop=False):
             if rc:
                 raise RuntimeError(f"pr_submit: {rc}")
             tickets.append((t.value, u0.shape))
+            if len(tickets) % 100 == 0:
+                print(f"served stream: {len(tickets)}/{n_req} submitted at "
+                      f"{time.perf_counter() - t_start:.0f} s",
+                      file=sys.stderr, flush=True)
         for t, shape in tickets:
             out = np.empty(shape)
             l = ctypes.c_double()
@@ -133,6 +137,10 @@ def serve_leg(n_req, rate, seed=4, timeout=300.0, closed_loop=False):
             if rc:
                 raise RuntimeError(f"request failed: {rc}")
             lat.append(l.value)
+            if len(lat) % 100 == 0:
+                print(f"served stream: {len(lat)}/{n_req} done at "
+                      f"{time.perf_counter() - t_start:.0f} s",
+                      file=sys.stderr, flush=True)
         wall = time.perf_counter() - t_start
     finally:
         lib.pr_server_destroy(h)
