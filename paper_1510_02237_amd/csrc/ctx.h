@@ -81,6 +81,8 @@ struct pr_ctx {
 
   // ----- subspace update in progress -----
   int upd_b = 0, upd_rho = 0;
+  int upd_verify = 0;  // columns the last second Cholesky-QR pass must have
+                       // kept, checked at the next wait (0: nothing pending)
 
   // ----- statistics -----
   pr_stats stats{};
@@ -118,7 +120,10 @@ int krylov_append(pr_ctx* c, const double* X0, const double* FX0, int b);
 int update_begin(pr_ctx* c, const double* X0, const double* FX0,
                  const double* GX0, int b);
 int update_mid(pr_ctx* c);
-int update_end(pr_ctx* c);
+// defer_check: the second pass's rank is checked by verify_second_pass at
+// the caller's next wait on the stream instead of now.
+int update_end(pr_ctx* c, bool defer_check = false);
+int verify_second_pass(pr_ctx* c);
 // Coarse initialisation q^0_{i+1} = G(q^0_i) (Algorithm 2, initialisation)
 // and the serial correction of iteration k, enqueued on the context stream.
 int coarse_init(pr_ctx* c);

@@ -741,14 +741,24 @@ int prh::update_mid(pr_ctx* c) {
   return PR_OK;
 }
 
-int prh::update_end(pr_ctx* c) {
-  const int b = c->upd_b, rho = c->upd_rho;
-  c->upd_b = 0;
-  if (b <= 0 || rho <= 0) return PR_OK;
-  if (c->h_ism[1] != rho)
+// The second pass must keep every column the first one kept; its rank
+// lands in h_ism[1] once the stream has passed the copy.
+int prh::verify_second_pass(pr_ctx* c) {
+  const int rho = c->upd_verify;
+  c->upd_verify = 0;
+  if (rho > 0 && c->h_ism[1] != rho)
     return set_error(c, PR_EDEVICE,
                      "second Cholesky-QR pass broke down (%d of %d columns)",
                      c->h_ism[1], rho);
+  return PR_OK;
+}
+
+int prh::update_end(pr_ctx* c, bool defer_check) {
+  const int b = c->upd_b, rho = c->upd_rho;
+  c->upd_b = 0;
+  if (b <= 0 || rho <= 0) return PR_OK;
+  c->upd_verify = rho;
+  if (!defer_check) RC(verify_second_pass(c));
   const int64_t ld = c->ld;
   RC(gemm_nn_chunked(c, c->S + (int64_t)c->r * ld, c->Yb, rho, c->T2, rho, rho,
                      1.0, 0.0));
@@ -898,6 +908,7 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
   } guard{ev};
 
   c->r = 0;
+  c->upd_verify = 0;
   HC(hipMemsetAsync(c->d_r11sq, 0, sizeof(double), s));
   HC(hipMemsetAsync(c->ism + 2, 0, sizeof(int), s));
   if (u0)
@@ -937,9 +948,12 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
       RC(update_begin(c, c->Q + (int64_t)k * ld, c->Qt + (int64_t)(k + 1) * ld,
                       c->GQ + (int64_t)k * ld, P - k));
       HC(hipStreamSynchronize(s));
+      // the rank of the previous update's second pass has landed too
+      RC(verify_second_pass(c));
       RC(update_mid(c));
-      HC(hipStreamSynchronize(s));
-      RC(update_end(c));
+      // the append needs only the first pass's rank; the second pass's is
+      // checked at the next wait, so the host does not stop the stream here
+      RC(update_end(c, true));
     }
     HC(hipEventRecord(ev[3 + 3 * k], s));
     const int rr = c->r;
@@ -979,6 +993,7 @@ static int solve_window(pr_ctx* c, const double* u0, int mem_in, int32_t K,
   HC(hipMemcpyAsync(c->h_ism + 2, c->ism + 2, sizeof(int), hipMemcpyDeviceToHost, s));
   HC(hipEventRecord(ev[2 + 3 * Keff], s));
   HC(hipStreamSynchronize(s));
+  RC(verify_second_pass(c));
   if (c->h_ism[2]) return set_error(c, PR_EDIVERGED, "iterate is not finite");
   auto el = [&](int a, int b) {
     float ms = 0;
