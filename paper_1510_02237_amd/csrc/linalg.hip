@@ -102,11 +102,12 @@ __global__ __launch_bounds__(GEMV_NT) void k_gemv_t(
   }
 }
 
+template <int E>
 __global__ __launch_bounds__(GEMV_NT) void k_colnorm2_part(
     const double* __restrict__ V, int64_t ld, int ncols, int64_t d,
     double* __restrict__ part) {
   __shared__ double sh[GEMV_JG][GEMV_NT / 64];
-  const int64_t x0 = (int64_t)blockIdx.x * GEMV_CHUNK;
+  const int64_t x0 = (int64_t)blockIdx.x * GEMV_NT * E;
   const int j0 = blockIdx.y * GEMV_JG;
   double acc[GEMV_JG];
 #pragma unroll
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(GEMV_NT) void k_colnorm2_part(
     const int j = j0 + q < ncols ? j0 + q : ncols - 1;
     const double* col = V + (int64_t)j * ld;
 #pragma unroll
-    for (int e = 0; e < GEMV_E; ++e) {
+    for (int e = 0; e < E; ++e) {
       const int64_t i = x0 + threadIdx.x + e * GEMV_NT;
       if (i < d) acc[q] += col[i] * col[i];
     }
@@ -810,6 +811,14 @@ __global__ void k_small_matmul(const double* __restrict__ T1, int b, int rho1,
 
 int gemv_t_blocks(int64_t d) { return (int)((d + GEMV_CHUNK - 1) / GEMV_CHUNK); }
 
+// Below 64 chunks of d the column norms take one element per thread, so
+// that small states (the paper's 40 x 40 grids: d = 4800) spread over more
+// workgroups instead of a few long dependent chains.
+int colnorm_blocks(int64_t d) {
+  return d < 64 * (int64_t)GEMV_CHUNK ? (int)((d + GEMV_NT - 1) / GEMV_NT)
+                                      : gemv_t_blocks(d);
+}
+
 namespace {
 // Slices of d for a projection onto ncols vectors: about GEMV_RESIDENT
 // workgroups in all, each slice at least GEMV_CHUNK elements.
@@ -852,10 +861,14 @@ hipError_t launch_reduce_cols(const double* part, int nblk, int ncols,
 hipError_t launch_colnorm2(const double* V, int64_t ld, int ncols, int64_t d,
                            double* part, double* nrm2, hipStream_t s) {
   if (ncols <= 0) return hipSuccess;
-  const int nblk = gemv_t_blocks(d);
-  hipLaunchKernelGGL(k_colnorm2_part,
-                     dim3(nblk, (ncols + GEMV_JG - 1) / GEMV_JG),
-                     dim3(GEMV_NT), 0, s, V, ld, ncols, d, part);
+  const int nblk = colnorm_blocks(d);
+  const dim3 grid(nblk, (ncols + GEMV_JG - 1) / GEMV_JG);
+  if (nblk == gemv_t_blocks(d))
+    hipLaunchKernelGGL(k_colnorm2_part<GEMV_E>, grid, dim3(GEMV_NT), 0, s, V,
+                       ld, ncols, d, part);
+  else
+    hipLaunchKernelGGL(k_colnorm2_part<1>, grid, dim3(GEMV_NT), 0, s, V, ld,
+                       ncols, d, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_reduce_cols(part, nblk, ncols, nrm2, s);

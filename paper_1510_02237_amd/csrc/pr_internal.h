@@ -142,8 +142,11 @@ hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s);
 // length d is stored vector after vector: V[j*ld + x].
 // ---------------------------------------------------------------------------
 
-// Chunks of d used by the column-norm partials (launch_colnorm2).
+// Chunks of d of the projections' partials (launch_gemv_t uses at most
+// this many slices).
 int gemv_t_blocks(int64_t d);
+// Partials per column of launch_colnorm2 (>= gemv_t_blocks(d)).
+int colnorm_blocks(int64_t d);
 // c = V^T x (deterministic: fixed slices of d, partial sums in part, summed
 // in a fixed order).  part needs gemv_t_part(d, ncols) doubles, at most
 // max(2048, ncols).
@@ -179,7 +182,7 @@ hipError_t launch_sub(double* y, const double* a, const double* b, int64_t n,
 // flag[0] |= 1 if any of the n doubles is not finite.
 hipError_t launch_check_finite(const double* v, int64_t n, int* flag,
                                hipStream_t s);
-// nrm2[j] = ||V[j]||^2 (deterministic; uses part[gemv_t_blocks(d)*ncols]).
+// nrm2[j] = ||V[j]||^2 (deterministic; uses part[colnorm_blocks(d)*ncols]).
 hipError_t launch_colnorm2(const double* V, int64_t ld, int ncols, int64_t d,
                            double* part, double* nrm2, hipStream_t s);
 
