@@ -944,9 +944,16 @@ int64_t tn_tile_splits(int64_t d, int tiles) {
   return std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, maxs));
 }
 
+// Shortest chunk of a small product: 512 elements, or d / 64 (at least 64)
+// on small states, which would otherwise give only a few workgroups.
+int64_t tn_min_chunk(int64_t d) {
+  return std::max<int64_t>(64, std::min<int64_t>(512, d / 64));
+}
+
 // Upper bound of the splits tn_shape picks at this d.
 int64_t tn_max_splits(int64_t d) {
-  return std::max<int64_t>(tn_tile_splits(d, 1), (d + 511) / 512);
+  const int64_t mc = tn_min_chunk(d);
+  return std::max<int64_t>(tn_tile_splits(d, 1), (d + mc - 1) / mc);
 }
 
 void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
@@ -957,13 +964,14 @@ void tn_shape(int M, int N, int64_t d, int* mt, int* nt, int* nsplit,
   int64_t ns = tn_tile_splits(d, tiles);
   // A wave computes one 32 x 32 quarter of a tile, and quarters beyond M
   // or N exit at once.  A small product (one or two active quarters per
-  // split) takes more, shorter chunks, down to 512 elements, so that about
-  // 1024 waves load operands at once; the partials to sum grow with them.
-  // active >= tiles, so ns stays <= ceil(1024 / tiles).
+  // split) takes more, shorter chunks, down to tn_min_chunk(d) elements, so
+  // that about 1024 waves load operands at once; the partials to sum grow
+  // with them.  active >= tiles, so ns stays <= ceil(1024 / tiles).
   const int64_t active = (int64_t)((M + 31) / 32) * ((N + 31) / 32);
+  const int64_t mc = tn_min_chunk(d);
   if (active <= 2)
     ns = std::max<int64_t>(ns, std::min<int64_t>((1024 + active - 1) / active,
-                                                 (d + 511) / 512));
+                                                 (d + mc - 1) / mc));
   int64_t k = (d + ns - 1) / ns;
   k = (k + 15) / 16 * 16;
   *kc = k;
