@@ -30,9 +30,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 BYTES_PER_POINT_STEP = 48.0   # read and write u, w, p once per RK-3 step
-# Stage form: stage 1 reads q^n and writes q*, stages 2 and 3 also read q^n
-# as their base: 48 + 72 + 72 bytes per point-step over three launches.
-STAGE_BYTES_PER_POINT_STEP = 192.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fine_step_traffic_c2_512x256.md")
 TRAFFIC_WORKLOAD = "c2_512x256"  # the workload the counters were taken on
 FINE_SRC = os.path.join(ROOT, "paper_1510_02237_amd", "csrc", "fine.hip")
@@ -260,12 +257,13 @@ def main():
         ctx.solve(u0_d, K, out=out)
     ms, ms_fine, pts, st = timed_solves(ctx, u0_d, K, out, args.steps)
     stage = stage_form(prob)
-    # one fused launch (or three stage launches) per RK-3 step of every
-    # iteration of every window
+    # one launch per RK-3 step of every iteration of every window: the fused
+    # step, or for per-row and per-column weights the fused three-stage tile
+    # kernel; either reads and writes u, w, p once per step
     n_fine_launches = (args.steps * prob.get("windows", 1) * min(K, prob["P"])
-                       * ctx_nf(prob) * (3 if stage else 1))
+                       * ctx_nf(prob))
     kernel_ms = ms_fine / n_fine_launches
-    bpp = STAGE_BYTES_PER_POINT_STEP if stage else BYTES_PER_POINT_STEP
+    bpp = BYTES_PER_POINT_STEP
     achieved = bpp * pts / (ms_fine * 1e-3) / 1e9
     # the counters hold for the tile and chunk shape of the workload they
     # were taken on; other grids use other tiles
@@ -291,7 +289,7 @@ def main():
         roofline=dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBPS,
                       unit="GB/s", frac=achieved / HBM_PEAK_GBPS,
                       traffic=traffic,
-                      kernel="k_stage" if stage else "k_fine_step",
+                      kernel="k_stage3" if stage else "k_fine_step",
                       kernel_avg_ms=kernel_ms,
                       bytes_per_point_step=bpp,
                       algorithmic_bytes_per_launch=bpp * pts / n_fine_launches,
@@ -340,9 +338,10 @@ def main():
 
 
 def stage_form(prob):
-    """True when the fine sweep of this workload runs as three stage
-    launches per RK-3 step (per-row and per-column advective weights: the
-    Section 3.1 pair, a z-velocity, a rotation or second-order acoustics)."""
+    """True when the fine sweep of this workload runs in the stage form
+    (per-row and per-column advective weights: the Section 3.1 pair, a
+    z-velocity, a rotation or second-order acoustics), whose RK-3 step is
+    one launch of the three-stage tile kernel."""
     return (prob.get("scheme", "split") == "rk3" or prob.get("V", 0.0) != 0.0
             or prob.get("gamma", 0.0) != 0.0
             or prob.get("fine_acoustic_order", 4) == 2)

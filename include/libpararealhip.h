@@ -70,7 +70,10 @@ enum { PR_MEM_HOST = 0, PR_MEM_DEVICE = 1 };
  *   PR_FORM_PLAIN:     one fused-step launch per slice per RK-3 step, slices
  *     in turn.
  *   PR_FORM_STAGEWISE: unfused comparison form, three stage launches per
- *     RK-3 step over all slices, neighbours read from global memory.
+ *     RK-3 step over all slices, neighbours read from global memory.  For
+ *     right-hand sides with per-row and per-column advective weights (see
+ *     fine_acoustic_order) it is the only form, and an RK-3 step is one
+ *     launch that runs the three stages on tiles held in LDS.
  * All forms give bitwise-identical fine results for the fused forms and
  * results equal to rounding for the stagewise form. */
 enum { PR_FORM_BATCHED = 0, PR_FORM_PLAIN = 1, PR_FORM_STAGEWISE = 2 };
@@ -150,11 +153,11 @@ typedef struct pr_opts {
                              always uses 2.
 
                              With V != 0, gamma != 0 or fine_acoustic_order
-                             = 2, F runs in PR_FORM_STAGEWISE (three stage
-                             launches per RK-3 step with per-row and
-                             per-column advective weights) and the slow
-                             tendency of G comes from a separate launch;
-                             the server accepts none of these.               */
+                             = 2, F runs in PR_FORM_STAGEWISE (per-row and
+                             per-column advective weights, one launch per
+                             RK-3 step) and the slow tendency of G comes
+                             from a separate launch; the server accepts
+                             none of these.                                  */
   int32_t coarse_order;   /* order of the upwind slow tendency of G in
                              PR_SCHEME_SPLIT: 1 (default, the main runs of
                              Section 3.2) or 3 (its less diffusive G; the

@@ -105,6 +105,13 @@ hipError_t launch_stage(const double* in, int64_t in_stride,
                         const double* base, int64_t base_stride, double* out,
                         int64_t out_stride, int nx, int nz, int nstates,
                         const StageCoef& c, double beta, hipStream_t s);
+// One RK-3 step of the same right-hand side: out = q + beta3 f(q2) with
+// q2 = q + beta2 f(q1), q1 = q + beta1 f(q), q = in; one launch, tiles of
+// 16 x 16 points with their halo in LDS.  in and out must not alias.
+hipError_t launch_stage3(const double* in, int64_t in_stride, double* out,
+                         int64_t out_stride, int nx, int nz, int nstates,
+                         const StageCoef& c, double beta1, double beta2,
+                         double beta3, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Coarse propagator (Section 3.2: partially split forward Euler; the slow

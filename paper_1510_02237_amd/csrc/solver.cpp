@@ -572,12 +572,9 @@ int prh::run_sweep(pr_ctx* c, const double* in, int64_t is, double* out,
       const int64_t dst_s = to_out ? os : ps;
       const double dt = c->fc.dt;
       if (c->tables_f) {
-        HC(launch_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns, c->sf,
-                        dt / 3.0, c->stream));
-        HC(launch_stage(A, ps, src, sst, B, ps, c->g.nx, c->g.nz, ns, c->sf,
-                        0.5 * dt, c->stream));
-        HC(launch_stage(B, ps, src, sst, dst, dst_s, c->g.nx, c->g.nz, ns,
-                        c->sf, dt, c->stream));
+        // the three stages in one launch (the stage buffers stay unused)
+        HC(launch_stage3(src, sst, dst, dst_s, c->g.nx, c->g.nz, ns, c->sf,
+                         dt / 3.0, 0.5 * dt, dt, c->stream));
       } else {
         HC(launch_fine_stage(src, sst, src, sst, A, ps, c->g.nx, c->g.nz, ns,
                              c->fc, dt / 3.0, c->sgn, c->stream));
@@ -619,19 +616,15 @@ int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
                     int64_t stride, double* pa, double* pb, double* R) {
   if (ns <= 0) return PR_OK;
   if (c->rk3) {
-    // n_g RK-3 steps of the upwind right-hand side: stages in pa and pb,
-    // steps alternating between out and R so that the last one lands in
-    // out and no stage writes its own input.
+    // n_g RK-3 steps of the upwind right-hand side, one launch each (all
+    // three stages), alternating between out and R so that the last one
+    // lands in out and no step writes its own input.
     const double dt = c->dt_g;
     const double* src = in;
     for (int st = 0; st < c->n_g; ++st) {
       double* dst = ((c->n_g - 1 - st) % 2 == 0) ? out : R;
-      HC(launch_stage(src, stride, src, stride, pa, stride, c->g.nx, c->g.nz,
-                      ns, c->sg, dt / 3.0, c->stream));
-      HC(launch_stage(pa, stride, src, stride, pb, stride, c->g.nx, c->g.nz,
-                      ns, c->sg, 0.5 * dt, c->stream));
-      HC(launch_stage(pb, stride, src, stride, dst, stride, c->g.nx, c->g.nz,
-                      ns, c->sg, dt, c->stream));
+      HC(launch_stage3(src, stride, dst, stride, c->g.nx, c->g.nz, ns, c->sg,
+                       dt / 3.0, 0.5 * dt, dt, c->stream));
       src = dst;
     }
     return PR_OK;
