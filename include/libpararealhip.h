@@ -155,13 +155,14 @@ typedef struct pr_opts {
                              With V != 0, gamma != 0 or fine_acoustic_order
                              = 2, F runs in PR_FORM_STAGEWISE (per-row and
                              per-column advective weights, one launch per
-                             RK-3 step) and the slow tendency of G comes
-                             from a separate launch; the server accepts
-                             none of these.                                  */
+                             RK-3 step) and each coarse step evaluates the
+                             slow tendency of G from per-row and per-column
+                             weights; the server accepts none of these.      */
   int32_t coarse_order;   /* order of the upwind slow tendency of G in
                              PR_SCHEME_SPLIT: 1 (default, the main runs of
                              Section 3.2) or 3 (its less diffusive G; the
-                             slow tendency then comes from the stage kernel).
+                             slow tendency then comes from per-row and
+                             per-column weights, as with V or gamma).
                              Forward Euler on the frozen third-order tendency
                              grows on long waves, so with a constant velocity
                              pr_create returns PR_EUNSTABLE.  The server

@@ -23,6 +23,13 @@
 // discarded) need no clamping.  Each thread owns the same MPT points in
 // every phase; their indices are computed once.  States are batched along
 // blockIdx.y.
+//
+// With a z-velocity, a rotation or the third-order slow tendency, R is the
+// sum of per-row x-weights and per-column z-weights times q (stencil within
+// 2 cells); the TAB instantiation evaluates it in the launch from a region
+// 2 cells wider on each side, where points closer than 2 cells to the
+// region's edge (more than 2 N_sound cells from the tile, so outside what
+// the substeps carry into it) keep R = 0.
 #include "pr_internal.h"
 
 namespace prh {
@@ -33,13 +40,18 @@ __device__ __forceinline__ int wrap(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-constexpr int HXM = 2 * kCoarseMaxSubPerLaunch + 1;
-constexpr int HZM = 2 * kCoarseMaxSubPerLaunch;
+// Largest halo: 2 cells per substep, plus 1 in x for the upwind R or 2 in
+// both directions for the table-driven R.
+template <bool TAB>
+constexpr int kHXM = 2 * kCoarseMaxSubPerLaunch + (TAB ? 2 : 1);
+template <bool TAB>
+constexpr int kHZM = 2 * kCoarseMaxSubPerLaunch + (TAB ? 2 : 0);
 
 // TX x TZ interior tile, NT threads.  A single state uses the shorter tile
 // (twice the workgroups for a latency-bound launch); batches use 32 x 32.
-template <int TX, int TZ, int NT>
+template <int TX, int TZ, int NT, bool TAB>
 __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
+  constexpr int HXM = kHXM<TAB>, HZM = kHZM<TAB>;
   constexpr int RXM = TX + 2 * HXM, RZM = TZ + 2 * HZM;
   constexpr int SX = RXM + 2;                     // padded LDS row stride
   constexpr int LDSN = (RZM + 2) * SX;
@@ -67,10 +79,10 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   const double* __restrict__ in = L.in + off;
   double* __restrict__ out = L.out + off;
   double* __restrict__ Rg = L.R ? L.R + off : nullptr;
-  const bool computeR = (L.flags & kCoarseComputeR) != 0;
+  const bool computeR = TAB || (L.flags & kCoarseComputeR) != 0;
   const bool storeR = (L.flags & kCoarseStoreR) != 0;
-  const int hx = 2 * L.nsub + (computeR ? 1 : 0);
-  const int hz = 2 * L.nsub;
+  const int hx = 2 * L.nsub + (TAB ? 2 : (computeR ? 1 : 0));
+  const int hz = 2 * L.nsub + (TAB ? 2 : 0);
   const int RX = TX + 2 * hx, RZ = TZ + 2 * hz;
   const int npts = RX * RZ;
   const int gx0 = xt * TX - hx, gz0 = zt * TZ - hz;
@@ -79,6 +91,20 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
 
   // Zero the whole LDS region once (the outer ring stays zero).
   for (int q = t; q < LDSN; q += NT) su[q] = sw[q] = sp[q] = su2[q] = sw2[q] = 0.0;
+  // Table-driven R: the x-weights of the region's rows and the z-weights
+  // of its columns, 7 each.
+  __shared__ double swt[TAB ? 7 * (RZM + RXM) : 1];
+  static_assert(!TAB || 7 * (RZM + RXM) <= NT, "one weight per thread");
+  if (TAB) {
+    if (t < 7 * RZ) {
+      const int b = t / 7;
+      swt[t] = L.wx[7 * (int64_t)wrap(gz0 + b, nz) + (t - 7 * b)];
+    } else if (t < 7 * (RZ + RX)) {
+      const int a = (t - 7 * RZ) / 7;
+      swt[7 * RZM + (t - 7 * RZ)] =
+          L.wz[7 * (int64_t)wrap(gx0 + a, nx) + (t - 7 * RZ - 7 * a)];
+    }
+  }
 
   int qi[MPT];       // LDS index of each owned point, -1 if none
   int64_t gi[MPT];   // global index of each owned point (wrapped)
@@ -125,7 +151,29 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
   for (int m = 0; m < MPT; ++m) {
     Ru[m] = Rw[m] = Rp[m] = 0.0;
     if (qi[m] < 0) continue;
-    if (computeR) {
+    if (TAB) {
+      const int q = qi[m];
+      const int a = q % SX - 1, b = q / SX - 1;
+      if (a < 2 || a >= RX - 2 || b < 2 || b >= RZ - 2) continue;
+      const double* wx = swt + 7 * b;
+      const double* wz = swt + 7 * RZM + 7 * a;
+      double au = 0.0, aw = 0.0, ap = 0.0;
+#pragma unroll
+      for (int o = -3; o <= 3; ++o) {
+        au += wx[o + 3] * su[q + o];
+        aw += wx[o + 3] * sw[q + o];
+        ap += wx[o + 3] * sp[q + o];
+      }
+#pragma unroll
+      for (int o = -3; o <= 3; ++o) {
+        au += wz[o + 3] * su[q + o * SX];
+        aw += wz[o + 3] * sw[q + o * SX];
+        ap += wz[o + 3] * sp[q + o * SX];
+      }
+      Ru[m] = au;
+      Rw[m] = aw;
+      Rp[m] = ap;
+    } else if (computeR) {
       const int q = qi[m], qn = q + dR;
       // cR (q_i - q_{i-1}) for U >= 0, cR (q_{i+1} - q_i) for U < 0
       Ru[m] = k.cR * (dR < 0 ? su[q] - su[qn] : su[qn] - su[q]);
@@ -206,14 +254,28 @@ __global__ __launch_bounds__(NT) void k_coarse(const CoarseLaunch L) {
 hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s) {
   if (L.nsub < 1 || L.nsub > kCoarseMaxSubPerLaunch || L.nstates < 1)
     return hipErrorInvalidValue;
+  const bool tab = (L.flags & kCoarseTablesR) != 0;
+  if (tab && (!L.wx || !L.wz)) return hipErrorInvalidValue;
   const int big = ((L.nx + 31) / 32) * ((L.nz + 31) / 32);
   auto pad8 = [](int t) { return (unsigned)(8 * ((t + 7) / 8)); };
-  if ((int64_t)big * L.nstates < 256) {
+  // The table-driven R has a halo 2 cells wider.  Few tiles (the paper's
+  // 40 x 40 grids): 16 x 8 tiles, whose 36 x 28 region gives every thread
+  // one point (the launch is latency-bound, so redundant halo work is
+  // cheaper than more points per thread); otherwise 32 x 32 (a 32 x 16
+  // tile would need more than the 128 VGPRs of a 1024-thread group).
+  if (tab && (int64_t)big * L.nstates < 256) {
+    const int tiles = ((L.nx + 15) / 16) * ((L.nz + 7) / 8);
+    hipLaunchKernelGGL((k_coarse<16, 8, 1024, true>), dim3(pad8(tiles), L.nstates),
+                       dim3(1024), 0, s, L);
+  } else if (tab) {
+    hipLaunchKernelGGL((k_coarse<32, 32, 1024, true>), dim3(pad8(big), L.nstates),
+                       dim3(1024), 0, s, L);
+  } else if ((int64_t)big * L.nstates < 256) {
     const int tiles = ((L.nx + 31) / 32) * ((L.nz + 15) / 16);
-    hipLaunchKernelGGL((k_coarse<32, 16, 1024>), dim3(pad8(tiles), L.nstates),
+    hipLaunchKernelGGL((k_coarse<32, 16, 1024, false>), dim3(pad8(tiles), L.nstates),
                        dim3(1024), 0, s, L);
   } else {
-    hipLaunchKernelGGL((k_coarse<32, 32, 1024>), dim3(pad8(big), L.nstates),
+    hipLaunchKernelGGL((k_coarse<32, 32, 1024, false>), dim3(pad8(big), L.nstates),
                        dim3(1024), 0, s, L);
   }
   return hipGetLastError();

@@ -98,13 +98,6 @@ struct StageCoef {
   double kxx, kxzu, kzz, kxzw;  // damping weights as in FineCoef (0 = none)
 };
 
-// out = base + beta * f(in) over ns states (each array with its own state
-// stride), or out = beta * f(in) when base is NULL; one point per thread,
-// neighbours read from global memory.
-hipError_t launch_stage(const double* in, int64_t in_stride,
-                        const double* base, int64_t base_stride, double* out,
-                        int64_t out_stride, int nx, int nz, int nstates,
-                        const StageCoef& c, double beta, hipStream_t s);
 // One RK-3 step of the same right-hand side: out = q + beta3 f(q2) with
 // q2 = q + beta2 f(q1), q1 = q + beta1 f(q), q = in; one launch, tiles of
 // 16 x 16 points with their halo in LDS.  in and out must not alias.
@@ -135,11 +128,17 @@ struct CoarseLaunch {
   int64_t stride;        // doubles between states (all three arrays)
   int32_t nx, nz, nstates;
   int32_t nsub;          // acoustic substeps done by this launch
-  int32_t flags;         // kCoarseComputeR | kCoarseStoreR, or 0 = load R
+  int32_t flags;         // kCoarseComputeR or kCoarseTablesR, either with
+                         // kCoarseStoreR; or 0 = load R
   CoarseCoef c;
+  const double* wx;      // kCoarseTablesR: device, [nz][7] x-weights of the
+  const double* wz;      // slow tendency per row, [nx][7] z-weights per
+                         // column (offsets -3..3; nonzero within -2..2)
 };
 constexpr int kCoarseComputeR = 1;
 constexpr int kCoarseStoreR = 2;
+constexpr int kCoarseTablesR = 4;  // R = sum of the row and column weights
+                                   // times q, evaluated in the launch
 constexpr int kCoarseMaxSubPerLaunch = 4;
 
 hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s);

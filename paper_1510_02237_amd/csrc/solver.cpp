@@ -331,9 +331,8 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
     RC(dalloc(c, &c->DX, w, "work"));
     RC(dalloc(c, &c->Yb, w, "work"));
     // third scratch block of run_coarse: the stored slow tendency (split
-    // scheme with more than one substep chunk or with the slow tendency
-    // from the stage kernel) or an RK-3 step (rk3)
-    if (c->coarse_chunks.size() > 1 || c->rk3 || c->tables_g)
+    // scheme with more than one substep chunk) or an RK-3 step (rk3)
+    if (c->coarse_chunks.size() > 1 || c->rk3)
       RC(dalloc(c, &c->Rb, w, "work"));
     c->wcap = wcap;
     changed = true;
@@ -634,12 +633,10 @@ int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
   const double* src = in;
   int q = 0;
   for (int step = 0; step < c->n_g; ++step) {
-    // With a z-velocity or a rotation the frozen slow tendency comes from
-    // the stage kernel (first-order upwind weights per row and column) and
-    // every substep launch loads it.
-    if (c->tables_g)
-      HC(launch_stage(src, stride, nullptr, 0, R, stride, c->g.nx, c->g.nz, ns,
-                      c->sg, 1.0, c->stream));
+    // The first launch of a step evaluates the frozen slow tendency (from
+    // the upwind difference, or with a z-velocity, a rotation or third
+    // order from the per-row and per-column weights) and, when the
+    // substeps take more than one launch, stores it for the others.
     for (int ch = 0; ch < nch; ++ch, ++q) {
       double* dst = (q == total - 1) ? out : ((q % 2 == 0) ? pa : pb);
       CoarseLaunch L;
@@ -651,10 +648,12 @@ int prh::run_coarse(pr_ctx* c, const double* in, double* out, int ns,
       L.nz = c->g.nz;
       L.nstates = ns;
       L.nsub = c->coarse_chunks[ch];
-      L.flags = (ch == 0 && !c->tables_g)
-                    ? (kCoarseComputeR | (nch > 1 ? kCoarseStoreR : 0))
-                    : 0;
+      L.flags = ch == 0 ? ((c->tables_g ? kCoarseTablesR : kCoarseComputeR) |
+                           (nch > 1 ? kCoarseStoreR : 0))
+                        : 0;
       L.c = c->cc;
+      L.wx = c->sg.wx;
+      L.wz = c->sg.wz;
       HC(launch_coarse(L, c->stream));
       src = dst;
     }

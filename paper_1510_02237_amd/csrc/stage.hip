@@ -1,39 +1,31 @@
-// Point-stencil stage kernel for right-hand sides whose advective weights
-// vary from row to row (x-direction) and from column to column
-// (z-direction):
+// RK-3 step kernel for right-hand sides whose advective weights vary from
+// row to row (x-direction) and from column to column (z-direction):
 //   f(q)_field = sum_{m=-3..3} (wx[j][m] q(i+m, j) + wz[i][m] q(i, j+m))
 //                - acoustic centred differences + grad-div damping.
-// It serves three right-hand sides:
+// It serves:
 //  * the propagator pair of the instability example (Section 3.1): RK-3
-//    stages with the sixth-order centred (F) or first-order upwind (G)
+//    steps with the sixth-order centred (F) or first-order upwind (G)
 //    advective flux, second-order acoustics, no damping, constant velocity
 //    (every row and every column has the same weights);
 //  * the fine propagator of Section 3.2 with an advection velocity that
 //    varies in space, (U + gamma (z - Lz/2), V - gamma (x - Lx/2)) (eq.
 //    adVel): the x-velocity is constant along a row and the z-velocity
 //    along a column, so the flux-form fifth-order upwind advection has one
-//    weight set (and one upwind side) per row and one per column;
-//  * the frozen slow tendency of the split coarse step with that velocity
-//    (first-order upwind weights, no acoustics, no damping, no base).
+//    weight set (and one upwind side) per row and one per column.
+// (The frozen slow tendency of the split coarse step with that velocity
+// uses the same kind of tables and is evaluated inside the coarse kernel.)
 // With d1(q) = q(+1) - q(-1) and d2(q) = q(+2) - q(-2) along an axis the
 // acoustic terms are
 //   u: -(ax1 d1x(p) + ax2 d2x(p))      w: -(az1 d1z(p) + az2 d2z(p))
 //   p: -((ax1 d1x(u) + ax2 d2x(u)) + (az1 d1z(w) + az2 d2z(w)))
 // (second order: ax1 = c_s/(2 dx), ax2 = 0; fourth order: ax1 = 8 c_s/(12
 // dx), ax2 = -c_s/(12 dx)) and the damping is that of the fused fine step.
-// These runs use small grids, where a step is bound by launch latency;
-// one point per thread with neighbours read from global memory (cached)
-// is the simple form that fits.
+// These runs use small grids, where a step is bound by launch latency, so
+// one launch does all three stages of a step on a tile held in LDS.
 #include "pr_internal.h"
 
 namespace prh {
 namespace {
-
-// Periodic index for i in [-3, n + 3) (a grid index plus a stencil offset
-// of at most 3; grids have n >= 8): two compares instead of a division.
-__device__ __forceinline__ int wrap(int i, int n) {
-  return i < 0 ? i + n : (i >= n ? i - n : i);
-}
 
 // f at one point; at(field, dx, dz) returns field 0 (u), 1 (w) or 2 (p) at
 // offset (dx, dz) from the point, wx and wz are the point's row and column
@@ -67,34 +59,6 @@ __device__ __forceinline__ void stage_point(const At& at, const double* wx,
   fu = au - dpx + c.kxx * gxx + c.kxzu * wxz;
   fw = aw - dpz + c.kzz * gzz + c.kxzw * uxz;
   fp = ap - (dux + dwz);
-}
-
-__global__ __launch_bounds__(256) void k_stage(
-    const double* __restrict__ in, int64_t is, const double* __restrict__ base,
-    int64_t bs, double* __restrict__ out, int64_t os, int nx, int nz,
-    const StageCoef c, double beta) {
-  const int64_t n = (int64_t)nx * nz;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= n) return;
-  const int64_t sl = blockIdx.y;
-  const double* Q = in + sl * is;
-  const int i = (int)(idx % nx), j = (int)(idx / nx);
-  auto at = [&](int f, int dx, int dz) {
-    return Q[f * n + (int64_t)wrap(j + dz, nz) * nx + wrap(i + dx, nx)];
-  };
-  double fu, fw, fp;
-  stage_point(at, c.wx + 7 * (int64_t)j, c.wz + 7 * (int64_t)i, c, fu, fw, fp);
-  double* O = out + sl * os;
-  if (base) {
-    const double* B = base + sl * bs;
-    O[idx] = B[idx] + beta * fu;
-    O[n + idx] = B[n + idx] + beta * fw;
-    O[2 * n + idx] = B[2 * n + idx] + beta * fp;
-  } else {
-    O[idx] = beta * fu;
-    O[n + idx] = beta * fw;
-    O[2 * n + idx] = beta * fp;
-  }
 }
 
 // All three stages of one RK-3 step in one launch.  A workgroup owns a
@@ -173,18 +137,6 @@ __global__ __launch_bounds__(S3_NT) void k_stage3(
 }
 
 }  // namespace
-
-hipError_t launch_stage(const double* in, int64_t in_stride,
-                        const double* base, int64_t base_stride, double* out,
-                        int64_t out_stride, int nx, int nz, int nstates,
-                        const StageCoef& c, double beta, hipStream_t s) {
-  if (nstates <= 0) return hipSuccess;
-  const int64_t n = (int64_t)nx * nz;
-  hipLaunchKernelGGL(k_stage, dim3((unsigned)((n + 255) / 256), nstates),
-                     dim3(256), 0, s, in, in_stride, base, base_stride, out,
-                     out_stride, nx, nz, c, beta);
-  return hipGetLastError();
-}
 
 hipError_t launch_stage3(const double* in, int64_t in_stride, double* out,
                          int64_t out_stride, int nx, int nz, int nstates,
