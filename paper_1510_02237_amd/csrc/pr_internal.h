@@ -151,7 +151,8 @@ hipError_t launch_coarse(const CoarseLaunch& L, hipStream_t s);
 // Chunks of d of the projections' partials (launch_gemv_t uses at most
 // this many slices).
 int gemv_t_blocks(int64_t d);
-// Partials per column of launch_colnorm2 (>= gemv_t_blocks(d)).
+// Partials per column of launch_colnorm2 (>= gemv_t_blocks(d)): one per 256
+// elements below 64 chunks, else gemv_t_blocks(d).  Not monotone in d.
 int colnorm_blocks(int64_t d);
 // c = V^T x (deterministic: fixed slices of d, partial sums in part, summed
 // in a fixed order).  part needs gemv_t_part(d, ncols) doubles, at most

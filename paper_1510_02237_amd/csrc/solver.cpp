@@ -360,9 +360,12 @@ int prh::ensure_arena(pr_ctx* c, int wcap, int rcap) {
   if (changed) {
     const int m = std::max(c->wcap, c->rcap);
     const int w = c->wcap;
-    // Partials: column norms use colnorm_blocks(ld) per column, projections
+    // Partials: column norms use colnorm_blocks(d) per column, projections
     // at most as many (their slice count is capped by gemv_t_blocks).
-    const size_t nblk = (size_t)colnorm_blocks(c->ld);
+    // colnorm_blocks is not monotone (it drops where small states switch to
+    // longer chunks), so take the larger of d and ld.
+    const size_t nblk =
+        (size_t)std::max(colnorm_blocks(c->d), colnorm_blocks(c->ld));
     size_t off = 0;
     const size_t part = nblk * m, cvec = m, cm = (size_t)c->rcap * w,
                  gram = (size_t)w * w, t = (size_t)w * w,

@@ -107,6 +107,22 @@ def test_solve_matches_oracle(nx, nz, P, U, K):
     assert ctx.stats()["rank"] == want["ranks"]
 
 
+def test_state_just_below_the_chunk_switch_matches_oracle():
+    """170 x 257 cells: d = 131070 lies just below 131072, where the column
+    norms switch from 256- to 2048-element slices, while the padded stride
+    ld = 131072 lies above it.  Their partial sums then take 512 slices per
+    column (64 at the length ld), and the solve must still match the
+    oracle's."""
+    prob = small_problem(170, 257, 3, U=0.1)
+    assert 3 * 170 * 257 == 131070
+    u0 = smooth_state(prob, 5)
+    say("solve 170x257 P=3 K=2")
+    want = _oracle_solve(prob, u0, 2)
+    ctx = binding.Context.from_problem(prob)
+    assert rel_l2(ctx.solve(u0, 2), want["q"][-1]) <= TOL_FINAL
+    assert ctx.stats()["rank"] == want["ranks"]
+
+
 def test_many_slices_matches_oracle():
     """P = 64 slices of two coarse steps at U = 0.3 (N_sound = 10: three
     substep launches per coarse step with the stored slow tendency): the
