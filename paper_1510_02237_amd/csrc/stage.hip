@@ -62,75 +62,64 @@ __device__ __forceinline__ void stage_point(const At& at, const double* wx,
 }
 
 // All three stages of one RK-3 step in one launch.  A workgroup owns a
-// T x T tile of one state and loads it with a halo of 9 cells (3 per
-// stage) into LDS, with the weights of the region's rows and columns;
-// stage s is evaluated on the region shrunk by 3 s, so the third stage
-// covers exactly the tile.  A 16 x 16 tile makes 784 + 484 + 256 point
-// evaluations for 256 outputs.  Launches with few tiles (the paper's 40 x
-// 40 grids) take 8 x 8 tiles instead: 400 + 196 + 64 evaluations per tile,
-// but more than twice the workgroups, each with less than half the LDS
-// work of the larger tile, for a launch that is bound by its latency.
-constexpr int S3_H = 9;
+// S3_T x S3_T tile of one state and loads it with a halo of 9 cells (3 per
+// stage) into LDS; stage s is evaluated on the region shrunk by 3 s, so the
+// third stage covers exactly the tile.  Per tile 784 + 484 + 256 point
+// evaluations for 256 outputs, against 3 launches of the one-point kernel.
+constexpr int S3_T = 16, S3_H = 9, S3_R = S3_T + 2 * S3_H, S3_RN = S3_R * S3_R;
+constexpr int S3_NT = 256;
 
 __device__ __forceinline__ int wrap_any(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
 
-template <int T, int NT>
-__global__ __launch_bounds__(NT) void k_stage3(
+__global__ __launch_bounds__(S3_NT) void k_stage3(
     const double* __restrict__ in, int64_t is, double* __restrict__ out,
     int64_t os, int nx, int nz, int xtiles, const StageCoef c, double b1,
     double b2, double b3) {
-  constexpr int R = T + 2 * S3_H, RN = R * R;
-  static_assert(NT >= R, "one thread per region row and column");
-  __shared__ double q0[3 * RN], s1[3 * RN], s2[3 * RN];
-  __shared__ int gi[R], gj[R];  // grid column / row of a region index
-  // x-weights of the region's rows and z-weights of its columns
-  __shared__ double swx[7 * R], swz[7 * R];
+  __shared__ double q0[3 * S3_RN], s1[3 * S3_RN], s2[3 * S3_RN];
+  __shared__ int gi[S3_R], gj[S3_R];  // grid column / row of a region index
   const int64_t n = (int64_t)nx * nz;
   const int xt = blockIdx.x % xtiles, zt = blockIdx.x / xtiles;
   const int64_t sl = blockIdx.y;
   const double* src = in + sl * is;
   double* dst = out + sl * os;
   const int t = threadIdx.x;
-  const int gx0 = xt * T - S3_H, gz0 = zt * T - S3_H;
-  if (t < R) {
+  const int gx0 = xt * S3_T - S3_H, gz0 = zt * S3_T - S3_H;
+  if (t < S3_R) {
     gi[t] = wrap_any(gx0 + t, nx);
     gj[t] = wrap_any(gz0 + t, nz);
   }
   __syncthreads();
-  for (int r = t; r < RN; r += NT) {
-    const int64_t g = (int64_t)gj[r / R] * nx + gi[r % R];
+  for (int r = t; r < S3_RN; r += S3_NT) {
+    const int64_t g = (int64_t)gj[r / S3_R] * nx + gi[r % S3_R];
     q0[r] = src[g];
-    q0[RN + r] = src[n + g];
-    q0[2 * RN + r] = src[2 * n + g];
-  }
-  for (int r = t; r < 7 * R; r += NT) {
-    swx[r] = c.wx[7 * (int64_t)gj[r / 7] + r % 7];
-    swz[r] = c.wz[7 * (int64_t)gi[r / 7] + r % 7];
+    q0[S3_RN + r] = src[n + g];
+    q0[2 * S3_RN + r] = src[2 * n + g];
   }
   __syncthreads();
   // Stage s over the region points at least 3 s from its edge.
   auto stage = [&](int s, const double* q, double beta, double* o,
                    bool last) {
-    const int lo = 3 * s, side = R - 6 * s;
-    for (int r = t; r < side * side; r += NT) {
+    const int lo = 3 * s, side = S3_R - 6 * s;
+    for (int r = t; r < side * side; r += S3_NT) {
       const int a = lo + r % side, b = lo + r / side;
-      const int p = b * R + a;
+      const int p = b * S3_R + a;
       auto at = [&](int f, int dx, int dz) {
-        return q[f * RN + p + dz * R + dx];
+        return q[f * S3_RN + p + dz * S3_R + dx];
       };
       double fu, fw, fp;
-      stage_point(at, swx + 7 * b, swz + 7 * a, c, fu, fw, fp);
-      const double nu = q0[p] + beta * fu, nw = q0[RN + p] + beta * fw,
-                   np = q0[2 * RN + p] + beta * fp;
+      stage_point(at, c.wx + 7 * (int64_t)gj[b], c.wz + 7 * (int64_t)gi[a], c,
+                  fu, fw, fp);
+      const double nu = q0[p] + beta * fu, nw = q0[S3_RN + p] + beta * fw,
+                   np = q0[2 * S3_RN + p] + beta * fp;
       if (!last) {
         o[p] = nu;
-        o[RN + p] = nw;
-        o[2 * RN + p] = np;
+        o[S3_RN + p] = nw;
+        o[2 * S3_RN + p] = np;
       } else {
-        const int x = xt * T + a - S3_H, z = zt * T + b - S3_H;
+        const int x = xt * S3_T + a - S3_H, z = zt * S3_T + b - S3_H;
         if (x < nx && z < nz) {
           const int64_t g = (int64_t)z * nx + x;
           dst[g] = nu;
@@ -154,18 +143,10 @@ hipError_t launch_stage3(const double* in, int64_t in_stride, double* out,
                          const StageCoef& c, double beta1, double beta2,
                          double beta3, hipStream_t s) {
   if (nstates <= 0) return hipSuccess;
-  const int64_t big = (int64_t)((nx + 15) / 16) * ((nz + 15) / 16) * nstates;
-  if (big < 256) {
-    const int xtiles = (nx + 7) / 8, ztiles = (nz + 7) / 8;
-    hipLaunchKernelGGL((k_stage3<8, 512>), dim3((unsigned)(xtiles * ztiles), nstates),
-                       dim3(512), 0, s, in, in_stride, out, out_stride, nx, nz,
-                       xtiles, c, beta1, beta2, beta3);
-  } else {
-    const int xtiles = (nx + 15) / 16, ztiles = (nz + 15) / 16;
-    hipLaunchKernelGGL((k_stage3<16, 1024>), dim3((unsigned)(xtiles * ztiles), nstates),
-                       dim3(1024), 0, s, in, in_stride, out, out_stride, nx, nz,
-                       xtiles, c, beta1, beta2, beta3);
-  }
+  const int xtiles = (nx + S3_T - 1) / S3_T, ztiles = (nz + S3_T - 1) / S3_T;
+  hipLaunchKernelGGL(k_stage3, dim3((unsigned)(xtiles * ztiles), nstates),
+                     dim3(S3_NT), 0, s, in, in_stride, out, out_stride, nx, nz,
+                     xtiles, c, beta1, beta2, beta3);
   return hipGetLastError();
 }
 
