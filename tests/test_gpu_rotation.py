@@ -1,13 +1,14 @@
 """The split scheme with a velocity that varies in space on the GPU against
 the oracle: the solid-body rotation of eq. adVel (Section 3.2), constant
 velocities with a z-component, and second-order fine acoustics.  F runs in
-the stage form with per-row and per-column advective weights; G's frozen
-slow tendency comes from the same stage kernel and every substep launch
-loads it.
+the stage form with per-row and per-column advective weights; the coarse
+kernel evaluates G's frozen slow tendency from the same kind of weights in
+the first launch of each coarse step, and with more than one substep launch
+stores it for the others.
 
-Sizes: the paper's 40 x 40 and 80 x 80 grids (the stage kernel's 256-point
-blocks end in a ragged tail on both), plus a non-square grid with a
-constant (U, V); N_sound 4 (one substep launch) and 6 (two).  The whole
+Sizes: the paper's 40 x 40 and 80 x 80 grids (the stage kernel's 16 x 16
+tiles end in a ragged tail on 40 x 40), plus a non-square grid with a
+constant (U, V); N_sound 4 (one substep launch), 6 and 8 (two).  The whole
 T = 2 runs of Tables 1 and 2 are checked against the oracle's own runs of
 the same cells stored in tests/golden (written by make_rotation_fixture.py).
 """
